@@ -1,0 +1,188 @@
+#!/usr/bin/env python
+"""Benchmark of the hybrid-VPL hot path on one MI355X.
+
+One step = G-buffer render + VPL generation (near patch VPLs + far walk) +
+the VPL gather (eq. (1), indirect part) for one view of the workload, with
+the scene (and its BVH) resident in HBM before the timed region.  The metric
+is VPL-pixel shading pairs per second including visibility: P * M pairs per
+step divided by the step time.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload room20k] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published)
+# algorithmic FLOPs (FMA = 2): per pair of the shading formula, and per cast
+# shadow ray its setup, per visited BVH2 node (two slab tests) and per
+# Moller-Trumbore triangle test
+FLOP_PAIR, FLOP_RAY, FLOP_NODE, FLOP_TRI = 27, 6, 24, 44
+
+
+def cpu_baseline(sc, target_s, seed=0):
+    """The FP64 oracle's gather timed on the host cores on a bounded pixel sample of the workload."""
+    import numpy as np
+    from oracle import oracle as orc
+
+    S = orc.Scene.from_dict(sc)
+    gb = S.gbuffer(sc["camera"])
+    g = S.generate(sc["camera"], sc["light"], sc["params"])
+    f32 = lambda a: a.astype(np.float32)  # noqa: E731
+    P = len(gb["tri"])
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(P)
+    threads = orc.num_threads()
+
+    def run(n):
+        idx = np.sort(order[:n])
+        t = time.perf_counter()
+        S.gather(f32(gb["pos"][idx]), f32(gb["nrm"][idx]), f32(gb["alb"][idx]), gb["tri"][idx], f32(g["pos"]),
+                 f32(g["nrm"]), f32(g["I"]), g["tri"], C=sc["params"]["g_clamp"], eps=sc["params"]["t_eps"],
+                 nthreads=threads)
+        return time.perf_counter() - t
+
+    probe = min(P, max(threads * 4, 64))
+    dt = run(probe)
+    n = int(min(P, max(probe, probe * target_s / max(dt, 1e-6))))
+    dt = run(n)
+    pairs = n * g["n"]
+    return dict(value=pairs / dt, unit="pairs/s", cores=threads, kind="oracle",
+                sample=f"{n} seeded random pixels of the {sc['camera']['width']}x{sc['camera']['height']} image x "
+                       f"{g['n']} VPLs ({pairs} pairs, FP64, {dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="room20k")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2203_11484_amd import scenes, vplg
+
+    sc = scenes.make_scene(args.workload)
+    cam, prm = sc["camera"], sc["params"]
+    W, H = cam["width"], cam["height"]
+    P = W * H
+    print(f"bench: {args.workload} {len(sc['tri'])} triangles, {W}x{H}, K={prm['k_near']} N_far={prm['n_far']}",
+          file=sys.stderr, flush=True)
+    torch.cuda.init()
+    ctx = vplg.context_create(0)
+    stream = torch.cuda.current_stream()
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"], stream)
+    gb = vplg.GBuffer(W, H)
+    rad = torch.zeros((3, H, W), dtype=torch.float32, device="cuda")
+    vid = vplg.vpls_generate(ctx, sid, cam, prm, stream)
+    M = vplg.vplset_count(ctx, vid)
+    gp = vplg.make_gather_params(prm)
+
+    def step(ev=None):
+        vplg.gbuffer_render(ctx, sid, cam, gb, stream)
+        vplg.vpls_regenerate(ctx, vid, cam, prm, stream)
+        if ev:
+            ev[0].record(stream)
+        vplg.gather(ctx, sid, vid, gb, rad, gp, stream)
+        if ev:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"bench: warmup done, M={M}", file=sys.stderr, flush=True)
+
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    g_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for i in range(args.steps):
+        step_ev[i].record(stream)
+        step(g_ev[i])
+    step_ev[-1].record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms_step = total_ms / args.steps
+    frame_ms = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps)])
+    gather_ms = np.array([a.elapsed_time(b) for a, b in g_ev])
+    print(f"bench: {args.steps} steps, {ms_step:.3f} ms/step, gather {gather_ms.mean():.3f} ms",
+          file=sys.stderr, flush=True)
+
+    # instrumented launch (untimed): pairs, shadow rays, BVH nodes, triangle tests
+    cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+    vplg.gather_counted(ctx, sid, vid, gb, rad, cnt, gp, stream)
+    torch.cuda.synchronize()
+    pairs_c, rays, nodes, tris = (int(x) for x in cnt.cpu().tolist())
+    stats = vplg.vplset_stats(ctx, vid)
+    valid = int((gb.tri >= 0).sum().item())
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    flops = FLOP_PAIR * pairs_c + FLOP_RAY * rays + FLOP_NODE * nodes + FLOP_TRI * tris
+    g_mean_s = gather_ms.mean() / 1e3
+    achieved = flops / g_mean_s / 1e12
+    pairs_step = P * M
+    out = {
+        "metric": "VPL-pixel shading pairs/sec incl. visibility (1 GPU)",
+        "value": pairs_step / (ms_step / 1e3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "triangles": int(len(sc["tri"])), "width": W, "height": H,
+                   "vpls": M, "near_vpls": int(stats["k_eff"]), "far_vpls": int(stats["n_far"]),
+                   "light": "point" if sc["light"]["kind"] == 0 else "quad", "g_clamp": prm["g_clamp"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_gather", "flop_per_launch": flops, "gather_ms": float(gather_ms.mean())},
+        "gather_pairs_per_s": pairs_step / g_mean_s,
+        "p50_frame_ms": float(np.percentile(frame_ms, 50)),
+        "p99_frame_ms": float(np.percentile(frame_ms, 99)),
+        "valid_pixel_frac": valid / P,
+        "shadow_ray_frac": rays / max(pairs_c, 1),
+        "nodes_per_ray": nodes / max(rays, 1),
+        "tris_per_ray": tris / max(rays, 1),
+        "ray_tri_tests_per_s": tris / g_mean_s,
+        "generation": {k: int(stats[k]) for k in ("n_patches", "n_near", "n_eligible", "n_paths")},
+    }
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+    vplg.context_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,244 @@
+/*
+ * vplg.h -- C ABI of the MI355X (gfx950) library for the hybrid virtual-point-
+ * light (VPL) method of "A Virtual Point Light Generation Method in
+ * Close-Range Area" (Jin, Wang, Zheng, Hua, Huo).
+ *
+ * The library renders the indirect part of eq. (1): for every G-buffer pixel
+ * y it sums, over all VPLs, the diffuse BRDF times the clamped geometry term
+ * times the visibility of the VPL.  The VPLs come from the paper's hybrid
+ * generation (Section "Close-Range VPL Sampling"): patch-stratified VPLs with
+ * the brightness of eq. (2) on the near faces that the camera frames, plus a
+ * sparse quasi-random walk (instant radiosity) whose hits on near faces are
+ * discarded.  Scene upload, G-buffer, generation and gather are device work
+ * behind this header; callers pass plain pointers.
+ *
+ * Conventions shared by every call:
+ *  - Return value: VPLG_OK (0) or a negative VPLG_E* code.  Nothing throws
+ *    across the ABI.  vplg_last_error() gives the calling thread's message of
+ *    its last failure.
+ *  - Ownership: the library owns scenes and VPL sets (device resident until
+ *    released; their bytes count against the context's HBM budget).  The
+ *    caller owns G-buffer and radiance buffers (device pointers) and streams.
+ *    Host input arrays may be freed when the call returns.
+ *  - Asynchrony: device calls only enqueue work on `stream` (a hipStream_t,
+ *    NULL = the null stream).  Argument and budget errors return at once;
+ *    a device fault surfaces as VPLG_EHIP at a later call that synchronises.
+ *  - Threads: a context is not thread-safe; use one per thread or lock.
+ *  - Units: world units are arbitrary but consistent; light power is radiant
+ *    flux per RGB channel; radiance is RGB float32.
+ */
+#ifndef VPLG_H
+#define VPLG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VPLG_OK = 0,
+    VPLG_EINVAL = -1,    /* bad argument (null pointer, size, unknown kind)     */
+    VPLG_ENOMEM = -2,    /* device allocation failed                            */
+    VPLG_EBUDGET = -3,   /* request would exceed the context's HBM budget       */
+    VPLG_ENOTFOUND = -4, /* unknown scene or VPL-set id                         */
+    VPLG_EHIP = -5,      /* HIP runtime error (launch, copy, device fault)      */
+    VPLG_EBUSY = -6,     /* object still in use                                 */
+    VPLG_ECANCELLED = -7,
+    VPLG_ETIMEOUT = -8
+};
+
+typedef struct vplg_context vplg_context;
+
+/* Message of the calling thread's most recent failure ("" if none).  The
+ * pointer stays valid until the thread's next failing call. */
+const char* vplg_last_error(void);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int vplg_version(void);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory that resident scenes and VPL sets may hold (0 = no cap). */
+int vplg_context_create(int device, uint64_t hbm_budget_bytes, vplg_context** out);
+/* Release every scene and VPL set of the context, then the context. */
+int vplg_context_destroy(vplg_context* ctx);
+/* Bytes currently held against the budget, and the budget (0 = none). */
+int vplg_context_usage(vplg_context* ctx, uint64_t* used_bytes, uint64_t* budget_bytes);
+
+/* ------------------------------------------------------------------------ */
+/* Scene upload                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Light of the scene.  kind 0: isotropic point light at pos (the paper's
+ * scenes use point lights, Section "Results").  kind 1: one-sided
+ * Lambertian parallelogram pos + s edge_u + t edge_v, s,t in [0,1], emitting
+ * toward normalize(edge_u x edge_v).  power: radiant flux per RGB channel. */
+typedef struct {
+    int32_t kind;
+    float pos[3];
+    float edge_u[3];
+    float edge_v[3];
+    float power[3];
+} vplg_light;
+
+/* Upload a triangle scene and build its ray-casting hierarchy (binned-SAH
+ * BVH built on the host, then resident on the device).
+ *   tri_xyz    host float32 [n_tris][3][3]: vertices A, B, C.  Faces are
+ *              one-sided (Section "Close-Range VPL Sampling"): the front is
+ *              the side toward (B - A) x (C - A).
+ *   tri_albedo host float32 [n_tris][3]: diffuse RGB albedo.
+ *   tri_flags  host uint8 [n_tris]: bit 0 = emitter (never receives VPLs).
+ *   light      host pointer, copied.
+ * On success *scene_id names the resident scene.  The call synchronises the
+ * stream before it returns.  EINVAL: n_tris < 1 or > 2^27, null pointer,
+ * non-finite vertex, unknown light kind.  EBUDGET / ENOMEM: no room. */
+int vplg_scene_upload(vplg_context* ctx, const float* tri_xyz, const float* tri_albedo, const uint8_t* tri_flags,
+                      int32_t n_tris, const vplg_light* light, void* stream, uint64_t* scene_id);
+int vplg_scene_release(vplg_context* ctx, uint64_t scene_id);
+
+typedef struct {
+    int32_t n_tris, n_nodes, n_leaves, max_depth;
+    uint64_t device_bytes;
+    float lo[3], hi[3]; /* scene bounding box */
+} vplg_scene_info;
+int vplg_scene_describe(vplg_context* ctx, uint64_t scene_id, vplg_scene_info* out);
+
+/* ------------------------------------------------------------------------ */
+/* G-buffer: the shading points y of eq. (1)                                */
+/* ------------------------------------------------------------------------ */
+
+/* Pinhole camera: basis f = normalize(target - eye), r = normalize(f x up),
+ * u = r x f; pixel (i, j) (row j = 0 at the top) looks along
+ * f + (2(i+1/2)/W - 1) tan(vfov/2) (W/H) r + (1 - 2(j+1/2)/H) tan(vfov/2) u. */
+typedef struct {
+    float eye[3], target[3], up[3];
+    float vfov_deg;
+    int32_t width, height;
+} vplg_camera;
+
+/* Caller-owned device planes of width * height elements, row-major:
+ * world position, unflipped unit face normal, albedo (float32), and the hit
+ * triangle (int32, -1 where the pixel ray misses; such pixels render 0). */
+typedef struct {
+    float* pos[3];
+    float* nrm[3];
+    float* alb[3];
+    int32_t* tri;
+    int32_t width, height;
+} vplg_gbuffer;
+
+/* Closest hit of one primary ray per pixel centre (float32). */
+int vplg_gbuffer_render(vplg_context* ctx, uint64_t scene_id, const vplg_camera* cam, const vplg_gbuffer* gb,
+                        void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* VPL generation (Section "Close-Range VPL Sampling")                      */
+/* ------------------------------------------------------------------------ */
+
+/* k_near     K, the number of patch VPLs (strata of the near-area CDF)
+ * n_far      number of far VPLs from the quasi-random walk
+ * max_bounces surface hits per walk path, 1 to 3
+ * max_paths  cap on walk paths (reaching it sets stats.flags bit 0)
+ * d_near     distance threshold of the near region
+ * patch_h    faces are refined into patches with edges <= patch_h
+ * t_eps      shadow-ray segment trim, as in the gather                      */
+typedef struct {
+    int32_t k_near, n_far, max_bounces, max_paths;
+    double d_near, patch_h, t_eps;
+} vplg_gen_params;
+
+typedef struct {
+    int64_t n_patches, n_near, n_eligible;
+    int64_t q_total;      /* f(N) in units of patch_h^2 / 2^24 */
+    int64_t k_eff;        /* patch VPLs made (0 when no near patch faces the light) */
+    int64_t n_far_target; /* n_far plus any unused near budget */
+    int64_t n_far, n_paths;
+    int64_t far_by_bounce[3];
+    int64_t flags;        /* bit 0: max_paths reached */
+    int64_t near_discarded;
+} vplg_gen_stats;
+
+/* Generate a VPL set for (scene, camera): near/far split of the patches,
+ * Morton-ordered fixed-point area CDF cut into k_near strata, one VPL per
+ * stratum with the brightness of eq. (2), then the walk.  Every integer
+ * decision is taken in FP64.  Device work is enqueued on `stream`; the
+ * first generation for a (scene, patch_h) pair synchronises once to size
+ * the patch arrays.  The VPL count is known after the stream completes
+ * (vplg_vplset_count / vplg_vplset_stats wait for it). */
+int vplg_vpls_generate(vplg_context* ctx, uint64_t scene_id, const vplg_camera* cam, const vplg_gen_params* p,
+                       void* stream, uint64_t* vplset_id);
+/* Generate again into an existing generated set (same scene, k_near, n_far
+ * and patch_h; camera and the other parameters may change), reusing its
+ * device buffers: no allocation and no synchronisation.  Work already queued
+ * that reads the set must be on the same stream or finished.  EINVAL if the
+ * budget parameters differ from the set's. */
+int vplg_vpls_regenerate(vplg_context* ctx, uint64_t vplset_id, const vplg_camera* cam, const vplg_gen_params* p,
+                         void* stream);
+/* Wait for the set's generation and return its statistics. */
+int vplg_vplset_stats(vplg_context* ctx, uint64_t vplset_id, vplg_gen_stats* out);
+/* Wait for the set and return its VPL count. */
+int vplg_vplset_count(vplg_context* ctx, uint64_t vplset_id, int32_t* n);
+
+/* Upload a VPL set from host arrays: pos, nrm, intensity float32 [n][3]
+ * (intensity I_k = flux / pi per channel), host_tri int32 [n] (the triangle a
+ * VPL lies on, excluded from its shadow rays; -1 for none). */
+int vplg_vpls_upload(vplg_context* ctx, const float* pos, const float* nrm, const float* intensity,
+                     const int32_t* host_tri, int32_t n, void* stream, uint64_t* vplset_id);
+/* Copy a set to host arrays of capacity `cap` (waits for it).  *n = count;
+ * EINVAL if cap < count. Any output pointer may be NULL. */
+int vplg_vpls_download(vplg_context* ctx, uint64_t vplset_id, float* pos, float* nrm, float* intensity,
+                       int32_t* host_tri, int32_t cap, int32_t* n);
+
+/* Intermediate arrays of a generated set, for verification (waits for it):
+ *   0 patch flags   uint8 [n_patches]   bit 0 near, bit 1 eligible
+ *   1 sorted        int32 [n_eligible]  eligible patch indices, Morton order
+ *   2 keys          uint32 [n_eligible] their Morton keys
+ *   3 prefix        int64 [n_eligible]  inclusive fixed-point area prefix f(i)
+ *   4 strata        int32 [k_eff]       stratum -> position in `sorted`
+ *   5 vpl path      int32 [count]       walk path of each VPL (0 = patch VPL)
+ *   6 vpl bounce    int32 [count]       bounce of each VPL (0 = patch VPL)
+ *   7 patch offsets int64 [n_tris + 1]  first patch index of each triangle
+ * *n_items = element count; EINVAL if cap_bytes is too small. */
+int vplg_vplset_debug(vplg_context* ctx, uint64_t vplset_id, int32_t what, void* host_buf, int64_t cap_bytes,
+                      int64_t* n_items);
+int vplg_vplset_release(vplg_context* ctx, uint64_t vplset_id);
+
+/* ------------------------------------------------------------------------ */
+/* Gather: eq. (1) without the direct term                                  */
+/* ------------------------------------------------------------------------ */
+
+/* g_clamp: C in min(C, cos_p cos_k / r^2) (> 0).  t_eps: shadow segments
+ * x + s (y - x) test s in (t_eps, 1 - t_eps), both host triangles excluded.
+ * tile_px, tile_vpl: 0 = library default. */
+typedef struct {
+    float g_clamp, t_eps;
+    int32_t tile_px, tile_vpl;
+} vplg_gather_params;
+
+/* radiance[c][p] = (albedo_p[c] / pi) * sum_k I_k[c] * min(C, max(0, n_p.d)
+ * max(0, -n_k.d) / |d|^4) * V(x_p, y_k), d = y_k - x_p, for every pixel of
+ * gb; pixels with tri < 0 get 0.  radiance: three caller-owned device planes
+ * of width * height float32.  Float32 arithmetic, per-tile partial sums
+ * added in a fixed order (deterministic). */
+int vplg_gather(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                float* const radiance[3], const vplg_gather_params* p, void* stream);
+
+/* The same kernel, instrumented: also adds to counters[0..3] (device uint64)
+ * the pairs evaluated, shadow rays cast, BVH nodes visited and ray-triangle
+ * tests performed.  For measurement; slower than vplg_gather. */
+int vplg_gather_counted(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                        float* const radiance[3], const vplg_gather_params* p, uint64_t* counters, void* stream);
+
+/* Visibility bits of the listed pixels against every VPL, computed for all
+ * pairs (no geometry-term culling), with the gather's own shadow-ray code.
+ * pixels: device int32 [n_px] pixel indices; vis_bits: device uint32
+ * [n_px][ceil(M / 32)], bit k % 32 of word k / 32 = V(x_p, y_k). */
+int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                                const int32_t* pixels, int32_t n_px, uint32_t* vis_bits,
+                                const vplg_gather_params* p, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VPLG_H */

@@ -1,0 +1,282 @@
+// Host binned-SAH BVH builder for the device layout described in vplg_impl.h.
+//
+// 32 bins per axis on the centroid bounds, surface-area cost with a unit
+// traversal cost and unit triangle cost, leaves of at most 8 triangles.  The
+// depth stays below kMaxDepth: deep subtrees fall back to median splits,
+// which halve the primitive count per level.  Child boxes are padded outward
+// so that FP32 and FP64 slab tests stay conservative.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vplg_impl.h"
+
+namespace vplg {
+
+namespace {
+
+constexpr int kBins = 32;
+constexpr int kLeafMax = 8;
+
+struct Box {
+    float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX};
+    float hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+    void grow(const float* p)
+    {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], p[k]);
+            hi[k] = std::max(hi[k], p[k]);
+        }
+    }
+    void grow(const Box& b)
+    {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], b.lo[k]);
+            hi[k] = std::max(hi[k], b.hi[k]);
+        }
+    }
+    bool empty() const { return lo[0] > hi[0]; }
+    double area() const
+    {
+        if (empty()) return 0.0;
+        double x = hi[0] - lo[0], y = hi[1] - lo[1], z = hi[2] - lo[2];
+        return 2.0 * (x * y + y * z + z * x);
+    }
+};
+
+struct BNode {
+    Box box;
+    int left = -1, right = -1;
+    int first = 0, count = 0;  // leaf iff count > 0
+    int depth = 0;
+};
+
+struct Builder {
+    const float* xyz;
+    std::vector<Box> pbox;
+    std::vector<float> cen;  // 3 per primitive
+    std::vector<int> idx;
+    std::vector<BNode> nodes;
+    int sah_depth_limit = 32;
+    int max_depth = 0;
+    int n_leaves = 0;
+
+    int make_leaf(int begin, int end, const Box& b, int depth)
+    {
+        BNode n;
+        n.box = b;
+        n.first = begin;
+        n.count = end - begin;
+        n.depth = depth;
+        nodes.push_back(n);
+        max_depth = std::max(max_depth, depth);
+        n_leaves++;
+        return (int)nodes.size() - 1;
+    }
+
+    int build(int begin, int end, int depth)
+    {
+        Box b, cb;
+        for (int i = begin; i < end; ++i) {
+            b.grow(pbox[idx[i]]);
+            cb.grow(&cen[3 * idx[i]]);
+        }
+        int n = end - begin;
+        if (n <= 2) return make_leaf(begin, end, b, depth);
+        int axis = 0;
+        float ext[3] = {cb.hi[0] - cb.lo[0], cb.hi[1] - cb.lo[1], cb.hi[2] - cb.lo[2]};
+        if (ext[1] > ext[axis]) axis = 1;
+        if (ext[2] > ext[axis]) axis = 2;
+        int mid = -1;
+        if (ext[axis] <= 0.f) {
+            if (n <= kLeafMax) return make_leaf(begin, end, b, depth);
+            mid = begin + n / 2;  // identical centroids: split the list
+        } else if (depth >= sah_depth_limit) {
+            mid = begin + n / 2;
+            std::nth_element(idx.begin() + begin, idx.begin() + mid, idx.begin() + end, [&](int a, int c) {
+                float ka = cen[3 * a + axis], kc = cen[3 * c + axis];
+                return ka < kc || (ka == kc && a < c);
+            });
+        } else {
+            double best_cost = DBL_MAX;
+            int best_axis = -1, best_split = -1;
+            for (int ax = 0; ax < 3; ++ax) {
+                if (ext[ax] <= 0.f) continue;
+                Box bins[kBins];
+                int cnt[kBins] = {0};
+                float scale = (float)kBins / ext[ax];
+                for (int i = begin; i < end; ++i) {
+                    int p = idx[i];
+                    int bi = std::min(kBins - 1, (int)((cen[3 * p + ax] - cb.lo[ax]) * scale));
+                    cnt[bi]++;
+                    bins[bi].grow(pbox[p]);
+                }
+                double rarea[kBins];
+                int rcnt[kBins];
+                Box acc;
+                int c = 0;
+                for (int i = kBins - 1; i > 0; --i) {
+                    acc.grow(bins[i]);
+                    c += cnt[i];
+                    rarea[i] = acc.area();
+                    rcnt[i] = c;
+                }
+                Box lacc;
+                int lc = 0;
+                for (int i = 0; i < kBins - 1; ++i) {
+                    lacc.grow(bins[i]);
+                    lc += cnt[i];
+                    if (lc == 0 || rcnt[i + 1] == 0) continue;
+                    double cost = lacc.area() * lc + rarea[i + 1] * rcnt[i + 1];
+                    if (cost < best_cost) {
+                        best_cost = cost;
+                        best_axis = ax;
+                        best_split = i;
+                    }
+                }
+            }
+            double leaf_cost = (double)n;
+            double split_cost = best_axis >= 0 ? 1.0 + best_cost / std::max(b.area(), 1e-30) : DBL_MAX;
+            if (n <= kLeafMax && split_cost >= leaf_cost) return make_leaf(begin, end, b, depth);
+            if (best_axis >= 0) {
+                float scale = (float)kBins / ext[best_axis];
+                float lo = cb.lo[best_axis];
+                auto it = std::partition(idx.begin() + begin, idx.begin() + end, [&](int p) {
+                    int bi = std::min(kBins - 1, (int)((cen[3 * p + best_axis] - lo) * scale));
+                    return bi <= best_split;
+                });
+                mid = (int)(it - idx.begin());
+            }
+            if (mid <= begin || mid >= end) {
+                mid = begin + n / 2;
+                std::nth_element(idx.begin() + begin, idx.begin() + mid, idx.begin() + end, [&](int a, int c) {
+                    float ka = cen[3 * a + axis], kc = cen[3 * c + axis];
+                    return ka < kc || (ka == kc && a < c);
+                });
+            }
+        }
+        BNode node;
+        node.box = b;
+        node.depth = depth;
+        nodes.push_back(node);
+        int me = (int)nodes.size() - 1;
+        int l = build(begin, mid, depth + 1);
+        int r = build(mid, end, depth + 1);
+        nodes[me].left = l;
+        nodes[me].right = r;
+        return me;
+    }
+};
+
+inline float pad_down(float v, float pad) { return std::nextafter(v - pad, -FLT_MAX); }
+inline float pad_up(float v, float pad) { return std::nextafter(v + pad, FLT_MAX); }
+
+}  // namespace
+
+// Build the BVH of T triangles (xyz: [T][3][3]).  Outputs the device node
+// array (4 float4 per node) and the leaf-ordered triangle array (3 float4
+// per triangle).  Returns false with a message on failure.
+bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vector<float4>& out_tris, int* n_leaves,
+               int* max_depth, std::string& err)
+{
+    Builder B;
+    B.xyz = xyz;
+    B.pbox.resize(T);
+    B.cen.resize(3 * (size_t)T);
+    B.idx.resize(T);
+    float maxabs = 0.f;
+    for (int t = 0; t < T; ++t) {
+        for (int v = 0; v < 3; ++v) {
+            const float* p = xyz + 9 * (size_t)t + 3 * v;
+            B.pbox[t].grow(p);
+            for (int k = 0; k < 3; ++k) maxabs = std::max(maxabs, std::fabs(p[k]));
+        }
+        for (int k = 0; k < 3; ++k) B.cen[3 * (size_t)t + k] = 0.5f * (B.pbox[t].lo[k] + B.pbox[t].hi[k]);
+        B.idx[t] = t;
+    }
+    // median levels needed below the SAH levels: ceil(log2(T / leaf)) + 1
+    int med = 1;
+    while ((1ll << med) * kLeafMax < (long long)T) med++;
+    B.sah_depth_limit = std::max(8, kMaxDepth - 2 - med);
+    B.nodes.reserve(2 * (size_t)T);
+    int root = B.build(0, T, 0);
+    if (B.max_depth > kMaxDepth - 1) {
+        err = "BVH deeper than the traversal stack";
+        return false;
+    }
+    // flatten: device nodes are the inner build nodes; a leaf-only tree gets
+    // an inner root with one absent child
+    std::vector<int> dev_of(B.nodes.size(), -1);
+    std::vector<int> order;
+    if (B.nodes[root].count > 0) {
+        order.push_back(-1);
+    } else {
+        std::vector<int> stack = {root};
+        while (!stack.empty()) {
+            int n = stack.back();
+            stack.pop_back();
+            dev_of[n] = (int)order.size();
+            order.push_back(n);
+            const BNode& bn = B.nodes[n];
+            if (B.nodes[bn.right].count == 0) stack.push_back(bn.right);
+            if (B.nodes[bn.left].count == 0) stack.push_back(bn.left);
+        }
+    }
+    float pad = 1e-6f * std::max(maxabs, 1.0f);
+    out_nodes.assign(4 * order.size(), make_float4(0, 0, 0, 0));
+    auto child = [&](int c, float* lo, float* hi, int* ref, int* cnt) {
+        if (c < 0) {
+            for (int k = 0; k < 3; ++k) { lo[k] = 1.0f; hi[k] = -1.0f; }
+            *ref = -1;
+            *cnt = 0;
+            return;
+        }
+        const BNode& n = B.nodes[c];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = pad_down(n.box.lo[k], pad);
+            hi[k] = pad_up(n.box.hi[k], pad);
+        }
+        if (n.count > 0) { *ref = n.first; *cnt = n.count; }
+        else { *ref = dev_of[c]; *cnt = 0; }
+    };
+    for (size_t i = 0; i < order.size(); ++i) {
+        int l, r;
+        if (order[i] < 0) { l = root; r = -1; }
+        else { l = B.nodes[order[i]].left; r = B.nodes[order[i]].right; }
+        float lo0[3], hi0[3], lo1[3], hi1[3];
+        int c0, c1, k0, k1;
+        child(l, lo0, hi0, &c0, &k0);
+        child(r, lo1, hi1, &c1, &k1);
+        float4* o = &out_nodes[4 * i];
+        o[0] = make_float4(lo0[0], hi0[0], lo0[1], hi0[1]);
+        o[1] = make_float4(lo1[0], hi1[0], lo1[1], hi1[1]);
+        o[2] = make_float4(lo0[2], hi0[2], lo1[2], hi1[2]);
+        float f[4];
+        int ints[4] = {c0, c1, k0, k1};
+        std::memcpy(f, ints, sizeof f);
+        o[3] = make_float4(f[0], f[1], f[2], f[3]);
+    }
+    out_tris.resize(3 * (size_t)T);
+    for (int i = 0; i < T; ++i) {
+        int t = B.idx[i];
+        const float* p = xyz + 9 * (size_t)t;
+        float idf;
+        std::memcpy(&idf, &t, sizeof idf);
+        out_tris[3 * i] = make_float4(p[0], p[1], p[2], idf);
+        float e1[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
+        float e2[3] = {p[6] - p[0], p[7] - p[1], p[8] - p[2]};
+        double n[3] = {(double)e1[1] * e2[2] - (double)e1[2] * e2[1], (double)e1[2] * e2[0] - (double)e1[0] * e2[2],
+                       (double)e1[0] * e2[1] - (double)e1[1] * e2[0]};
+        double cut = kParallelTau * kParallelTau * (n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        out_tris[3 * i + 1] = make_float4(e1[0], e1[1], e1[2], 0.f);
+        out_tris[3 * i + 2] = make_float4(e2[0], e2[1], e2[2], (float)cut);
+    }
+    *n_leaves = B.n_leaves;
+    *max_depth = B.max_depth;
+    return true;
+}
+
+}  // namespace vplg

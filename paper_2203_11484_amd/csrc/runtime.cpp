@@ -1,0 +1,798 @@
+// Host runtime behind include/vplg.h: contexts with an HBM budget, resident
+// scenes (host SAH BVH) and VPL sets, argument checking, and the dispatch of
+// the G-buffer, generation and gather kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "vplg.h"
+#include "vplg_impl.h"
+
+namespace vplg {
+bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vector<float4>& out_tris, int* n_leaves,
+               int* max_depth, std::string& err);
+}
+
+using namespace vplg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(VPLG_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct Alloc {
+    void* p;
+    size_t bytes;
+};
+
+struct PatchIndex {
+    double h;
+    int32_t* level;
+    long long* off;
+    long long total;
+};
+
+struct SceneObj {
+    DevScene dev;
+    DevLight light;
+    std::vector<Alloc> allocs;
+    uint64_t bytes = 0;
+    vplg_scene_info info;
+    std::vector<PatchIndex> patches;
+};
+
+struct VplSetObj {
+    DevVpls dev;
+    std::vector<Alloc> allocs;
+    uint64_t bytes = 0;
+    bool generated = false;
+    GenBuffers gen;
+    int k_near = 0;
+    int n_far = 0;
+    int n_tris = 0;
+    uint64_t scene_id = 0;
+    double patch_h = 0.0;
+    hipEvent_t done = nullptr;
+};
+
+}  // namespace
+
+struct vplg_context {
+    int device = 0;
+    uint64_t budget = 0, used = 0;
+    uint64_t next_id = 1;
+    std::map<uint64_t, SceneObj*> scenes;
+    std::map<uint64_t, VplSetObj*> sets;
+};
+
+namespace {
+
+int dalloc(vplg_context* ctx, std::vector<Alloc>& list, uint64_t& acc, size_t bytes, void** out)
+{
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+        return fail(VPLG_EBUDGET, "HBM budget exceeded: %llu used + %llu requested > %llu",
+                    (unsigned long long)ctx->used, (unsigned long long)bytes, (unsigned long long)ctx->budget);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(VPLG_ENOMEM, "hipMalloc(%llu) failed: %s", (unsigned long long)bytes, hipGetErrorString(e));
+    }
+    list.push_back({p, bytes});
+    acc += bytes;
+    ctx->used += bytes;
+    *out = p;
+    return VPLG_OK;
+}
+
+template <class T>
+int dalloc_n(vplg_context* ctx, std::vector<Alloc>& list, uint64_t& acc, size_t n, T** out)
+{
+    void* p = nullptr;
+    int rc = dalloc(ctx, list, acc, n * sizeof(T), &p);
+    *out = (T*)p;
+    return rc;
+}
+
+void free_all(vplg_context* ctx, std::vector<Alloc>& list)
+{
+    for (auto& a : list) {
+        (void)hipFree(a.p);
+        ctx->used -= a.bytes;
+    }
+    list.clear();
+}
+
+int set_device(vplg_context* ctx)
+{
+    if (!ctx) return fail(VPLG_EINVAL, "null context");
+    HIPCHK(hipSetDevice(ctx->device));
+    return VPLG_OK;
+}
+
+SceneObj* find_scene(vplg_context* ctx, uint64_t id)
+{
+    auto it = ctx->scenes.find(id);
+    return it == ctx->scenes.end() ? nullptr : it->second;
+}
+
+VplSetObj* find_set(vplg_context* ctx, uint64_t id)
+{
+    auto it = ctx->sets.find(id);
+    return it == ctx->sets.end() ? nullptr : it->second;
+}
+
+void release_set(vplg_context* ctx, VplSetObj* v)
+{
+    if (v->done) (void)hipEventDestroy(v->done);
+    free_all(ctx, v->allocs);
+    delete v;
+}
+
+// Camera basis in FP64: f = normalize(target - eye), r = normalize(f x up),
+// u = r x f, th = tan(vfov / 2), tx = th W / H (fixed operation order).
+CamBasis cam_basis(const vplg_camera* c)
+{
+    CamBasis k;
+    double eye[3], tg[3], up[3];
+    for (int i = 0; i < 3; ++i) {
+        eye[i] = c->eye[i];
+        tg[i] = c->target[i];
+        up[i] = c->up[i];
+    }
+    double f[3] = {tg[0] - eye[0], tg[1] - eye[1], tg[2] - eye[2]};
+    double lf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    for (int i = 0; i < 3; ++i) f[i] = f[i] / lf;
+    double r[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+    double lr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    for (int i = 0; i < 3; ++i) r[i] = r[i] / lr;
+    double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+    for (int i = 0; i < 3; ++i) {
+        k.eye[i] = eye[i];
+        k.f[i] = f[i];
+        k.r[i] = r[i];
+        k.u[i] = u[i];
+    }
+    k.width = c->width;
+    k.height = c->height;
+    k.th = std::tan((double)c->vfov_deg * (3.14159265358979323846 / 360.0));
+    k.tx = k.th * ((double)c->width / (double)c->height);
+    return k;
+}
+
+int check_camera(const vplg_camera* c)
+{
+    if (!c) return fail(VPLG_EINVAL, "null camera");
+    if (c->width < 1 || c->height < 1 || (long long)c->width * c->height > (1ll << 28))
+        return fail(VPLG_EINVAL, "bad image size %d x %d", c->width, c->height);
+    if (!(c->vfov_deg > 0.f && c->vfov_deg < 180.f)) return fail(VPLG_EINVAL, "vfov must be in (0, 180)");
+    double f[3] = {(double)c->target[0] - c->eye[0], (double)c->target[1] - c->eye[1],
+                   (double)c->target[2] - c->eye[2]};
+    double cr[3] = {f[1] * c->up[2] - f[2] * c->up[1], f[2] * c->up[0] - f[0] * c->up[2],
+                    f[0] * c->up[1] - f[1] * c->up[0]};
+    if (f[0] * f[0] + f[1] * f[1] + f[2] * f[2] == 0.0 || cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2] == 0.0)
+        return fail(VPLG_EINVAL, "degenerate camera basis");
+    return VPLG_OK;
+}
+
+int check_gbuffer(const vplg_gbuffer* gb)
+{
+    if (!gb) return fail(VPLG_EINVAL, "null gbuffer");
+    for (int c = 0; c < 3; ++c)
+        if (!gb->pos[c] || !gb->nrm[c] || !gb->alb[c]) return fail(VPLG_EINVAL, "null gbuffer plane");
+    if (!gb->tri) return fail(VPLG_EINVAL, "null gbuffer tri plane");
+    if (gb->width < 1 || gb->height < 1 || (long long)gb->width * gb->height > (1ll << 28))
+        return fail(VPLG_EINVAL, "bad gbuffer size %d x %d", gb->width, gb->height);
+    return VPLG_OK;
+}
+
+DevGBuffer dev_gbuffer(const vplg_gbuffer* gb)
+{
+    DevGBuffer d;
+    for (int c = 0; c < 3; ++c) {
+        d.pos[c] = gb->pos[c];
+        d.nrm[c] = gb->nrm[c];
+        d.alb[c] = gb->alb[c];
+    }
+    d.tri = gb->tri;
+    d.width = gb->width;
+    d.height = gb->height;
+    return d;
+}
+
+int wait_set(VplSetObj* v)
+{
+    if (v->done) HIPCHK(hipEventSynchronize(v->done));
+    return VPLG_OK;
+}
+
+int set_count(VplSetObj* v, int32_t* n)
+{
+    int rc = wait_set(v);
+    if (rc) return rc;
+    HIPCHK(hipMemcpy(n, v->dev.count, sizeof(int32_t), hipMemcpyDeviceToHost));
+    return VPLG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vplg_last_error(void) { return g_err.c_str(); }
+
+int vplg_version(void) { return 10000; }
+
+int vplg_context_create(int device, uint64_t hbm_budget_bytes, vplg_context** out)
+{
+    if (!out) return fail(VPLG_EINVAL, "null output pointer");
+    *out = nullptr;
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(VPLG_EINVAL, "device %d out of range (%d devices)", device, n);
+    HIPCHK(hipSetDevice(device));
+    auto* ctx = new vplg_context;
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    *out = ctx;
+    return VPLG_OK;
+}
+
+int vplg_context_destroy(vplg_context* ctx)
+{
+    if (!ctx) return fail(VPLG_EINVAL, "null context");
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->sets) release_set(ctx, kv.second);
+    for (auto& kv : ctx->scenes) {
+        free_all(ctx, kv.second->allocs);
+        delete kv.second;
+    }
+    delete ctx;
+    return VPLG_OK;
+}
+
+int vplg_context_usage(vplg_context* ctx, uint64_t* used, uint64_t* budget)
+{
+    if (!ctx) return fail(VPLG_EINVAL, "null context");
+    if (used) *used = ctx->used;
+    if (budget) *budget = ctx->budget;
+    return VPLG_OK;
+}
+
+int vplg_scene_upload(vplg_context* ctx, const float* tri_xyz, const float* tri_albedo, const uint8_t* tri_flags,
+                      int32_t n_tris, const vplg_light* light, void* stream, uint64_t* scene_id)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (!tri_xyz || !tri_albedo || !tri_flags || !light || !scene_id) return fail(VPLG_EINVAL, "null argument");
+    if (n_tris < 1 || n_tris > (1 << 27)) return fail(VPLG_EINVAL, "n_tris %d out of range", n_tris);
+    if (light->kind != 0 && light->kind != 1) return fail(VPLG_EINVAL, "unknown light kind %d", light->kind);
+    for (size_t i = 0; i < 9 * (size_t)n_tris; ++i)
+        if (!std::isfinite(tri_xyz[i])) return fail(VPLG_EINVAL, "non-finite vertex coordinate at %zu", i);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<float4> nodes, tris;
+    int n_leaves = 0, depth = 0;
+    std::string err;
+    if (!build_bvh(tri_xyz, n_tris, nodes, tris, &n_leaves, &depth, err)) return fail(VPLG_EINVAL, "%s", err.c_str());
+    std::vector<float4> normals(n_tris);
+    SceneObj* so = new SceneObj;
+    DevScene& d = so->dev;
+    for (int k = 0; k < 3; ++k) {
+        d.lo[k] = tri_xyz[k];
+        d.hi[k] = tri_xyz[k];
+    }
+    for (int t = 0; t < n_tris; ++t) {
+        const float* p = tri_xyz + 9 * (size_t)t;
+        double a[3], b[3], c[3];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = p[k];
+            b[k] = p[3 + k];
+            c[k] = p[6 + k];
+            for (int v = 0; v < 3; ++v) {
+                d.lo[k] = std::min(d.lo[k], p[3 * v + k]);
+                d.hi[k] = std::max(d.hi[k], p[3 * v + k]);
+            }
+        }
+        double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (l > 0) normals[t] = make_float4((float)(n[0] / l), (float)(n[1] / l), (float)(n[2] / l), 0.f);
+        else normals[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float4 *dn = nullptr, *dt = nullptr, *dnorm = nullptr;
+    float *dxyz = nullptr, *dalb = nullptr;
+    uint8_t* dfl = nullptr;
+    if ((rc = dalloc_n(ctx, so->allocs, so->bytes, nodes.size(), &dn)) ||
+        (rc = dalloc_n(ctx, so->allocs, so->bytes, tris.size(), &dt)) ||
+        (rc = dalloc_n(ctx, so->allocs, so->bytes, 9 * (size_t)n_tris, &dxyz)) ||
+        (rc = dalloc_n(ctx, so->allocs, so->bytes, 3 * (size_t)n_tris, &dalb)) ||
+        (rc = dalloc_n(ctx, so->allocs, so->bytes, (size_t)n_tris, &dfl)) ||
+        (rc = dalloc_n(ctx, so->allocs, so->bytes, (size_t)n_tris, &dnorm))) {
+        free_all(ctx, so->allocs);
+        delete so;
+        return rc;
+    }
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(dn, nodes.data(), nodes.size() * sizeof(float4), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dt, tris.data(), tris.size() * sizeof(float4), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dxyz, tri_xyz, 36 * (size_t)n_tris, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dalb, tri_albedo, 12 * (size_t)n_tris, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dfl, tri_flags, (size_t)n_tris, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dnorm, normals.data(), normals.size() * sizeof(float4), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_all(ctx, so->allocs);
+        delete so;
+        return fail(VPLG_EHIP, "scene upload copy failed: %s", hipGetErrorString(e));
+    }
+    d.n_tris = n_tris;
+    d.n_nodes = (int)(nodes.size() / 4);
+    d.nodes = dn;
+    d.tris = dt;
+    d.xyz = dxyz;
+    d.albedo = dalb;
+    d.flags = dfl;
+    d.normals = dnorm;
+    so->light.kind = light->kind;
+    for (int k = 0; k < 3; ++k) {
+        so->light.pos[k] = light->pos[k];
+        so->light.eu[k] = light->edge_u[k];
+        so->light.ev[k] = light->edge_v[k];
+        so->light.power[k] = light->power[k];
+    }
+    so->info.n_tris = n_tris;
+    so->info.n_nodes = d.n_nodes;
+    so->info.n_leaves = n_leaves;
+    so->info.max_depth = depth;
+    so->info.device_bytes = so->bytes;
+    for (int k = 0; k < 3; ++k) {
+        so->info.lo[k] = d.lo[k];
+        so->info.hi[k] = d.hi[k];
+    }
+    uint64_t id = ctx->next_id++;
+    ctx->scenes[id] = so;
+    *scene_id = id;
+    return VPLG_OK;
+}
+
+int vplg_scene_release(vplg_context* ctx, uint64_t scene_id)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    SceneObj* so = find_scene(ctx, scene_id);
+    if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
+    HIPCHK(hipDeviceSynchronize());
+    free_all(ctx, so->allocs);
+    delete so;
+    ctx->scenes.erase(scene_id);
+    return VPLG_OK;
+}
+
+int vplg_scene_describe(vplg_context* ctx, uint64_t scene_id, vplg_scene_info* out)
+{
+    if (!ctx || !out) return fail(VPLG_EINVAL, "null argument");
+    SceneObj* so = find_scene(ctx, scene_id);
+    if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
+    *out = so->info;
+    out->device_bytes = so->bytes;
+    return VPLG_OK;
+}
+
+int vplg_gbuffer_render(vplg_context* ctx, uint64_t scene_id, const vplg_camera* cam, const vplg_gbuffer* gb,
+                        void* stream)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    SceneObj* so = find_scene(ctx, scene_id);
+    if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
+    if ((rc = check_camera(cam)) || (rc = check_gbuffer(gb))) return rc;
+    if (gb->width != cam->width || gb->height != cam->height)
+        return fail(VPLG_EINVAL, "gbuffer %dx%d does not match camera %dx%d", gb->width, gb->height, cam->width,
+                    cam->height);
+    CamBasis k = cam_basis(cam);
+    GBufferArgs a;
+    a.scene = so->dev;
+    for (int i = 0; i < 3; ++i) {
+        a.eye[i] = (float)k.eye[i];
+        a.f[i] = (float)k.f[i];
+        a.r[i] = (float)k.r[i];
+        a.u[i] = (float)k.u[i];
+        a.pos[i] = gb->pos[i];
+        a.nrm[i] = gb->nrm[i];
+        a.alb[i] = gb->alb[i];
+    }
+    a.th = (float)k.th;
+    a.tx = (float)k.tx;
+    a.tri = gb->tri;
+    a.width = gb->width;
+    a.height = gb->height;
+    HIPCHK(launch_gbuffer(a, (hipStream_t)stream));
+    return VPLG_OK;
+}
+
+static int check_gen_params(const vplg_gen_params* p)
+{
+    if (!p) return fail(VPLG_EINVAL, "null parameters");
+    if (p->k_near < 0 || p->n_far < 0 || (long long)p->k_near + p->n_far > (1 << 26))
+        return fail(VPLG_EINVAL, "bad VPL budget k_near=%d n_far=%d", p->k_near, p->n_far);
+    if (p->max_bounces < 1 || p->max_bounces > 3) return fail(VPLG_EINVAL, "max_bounces must be in [1, 3]");
+    if (p->max_paths < 1) return fail(VPLG_EINVAL, "max_paths must be >= 1");
+    if (!(p->patch_h > 0.0) || !std::isfinite(p->patch_h)) return fail(VPLG_EINVAL, "patch_h must be > 0");
+    if (!(p->d_near >= 0.0)) return fail(VPLG_EINVAL, "d_near must be >= 0");
+    if (!(p->t_eps >= 0.0 && p->t_eps < 0.5)) return fail(VPLG_EINVAL, "t_eps must be in [0, 0.5)");
+    return VPLG_OK;
+}
+
+int vplg_vpls_generate(vplg_context* ctx, uint64_t scene_id, const vplg_camera* cam, const vplg_gen_params* p,
+                       void* stream, uint64_t* vplset_id)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (!vplset_id) return fail(VPLG_EINVAL, "null argument");
+    SceneObj* so = find_scene(ctx, scene_id);
+    if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
+    if ((rc = check_camera(cam)) || (rc = check_gen_params(p))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int T = so->dev.n_tris;
+    // patch index of the scene for this h (computed once, then resident)
+    PatchIndex* pi = nullptr;
+    for (auto& x : so->patches)
+        if (x.h == p->patch_h) pi = &x;
+    if (!pi) {
+        PatchIndex x;
+        x.h = p->patch_h;
+        long long* counts = nullptr;
+        std::vector<Alloc> tmp;
+        uint64_t tmp_bytes = 0;
+        long long* scan_tmp = nullptr;
+        int need = scan_tmp_needed(T);
+        if ((rc = dalloc_n(ctx, so->allocs, so->bytes, (size_t)T, &x.level)) ||
+            (rc = dalloc_n(ctx, so->allocs, so->bytes, (size_t)T + 1, &x.off)) ||
+            (rc = dalloc_n(ctx, tmp, tmp_bytes, (size_t)T, &counts)) ||
+            (rc = dalloc_n(ctx, tmp, tmp_bytes, (size_t)need, &scan_tmp))) {
+            free_all(ctx, tmp);
+            return rc;
+        }
+        hipError_t e = launch_patch_levels(so->dev, p->patch_h, x.level, counts, s);
+        if (e == hipSuccess) e = launch_scan_i64(counts, x.off, T, scan_tmp, need, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&x.total, x.off + T, sizeof(long long), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        free_all(ctx, tmp);
+        if (e != hipSuccess) return fail(VPLG_EHIP, "patch index: %s", hipGetErrorString(e));
+        if (x.total > (1ll << 30)) return fail(VPLG_EINVAL, "too many patches (%lld) for patch_h", x.total);
+        so->patches.push_back(x);
+        pi = &so->patches.back();
+        so->info.device_bytes = so->bytes;
+    }
+    const long long NP = pi->total;
+    const int cap = p->k_near + p->n_far;
+    auto* v = new VplSetObj;
+    v->generated = true;
+    v->k_near = p->k_near;
+    v->n_far = p->n_far;
+    v->n_tris = T;
+    v->scene_id = scene_id;
+    v->patch_h = p->patch_h;
+    DevVpls& dv = v->dev;
+    GenBuffers& b = v->gen;
+    std::memset(&b, 0, sizeof b);
+    b.n_patches = (int)NP;
+    b.level = pi->level;
+    b.patch_off = pi->off;
+    long long n2 = 2048;
+    while (n2 < NP) n2 <<= 1;
+    int target = cap;
+    int batch = 4096;
+    while (batch < 4 * target && batch < 65536) batch <<= 1;
+    b.batch = batch;
+    b.scan_tmp_len = scan_tmp_needed((int)std::max<long long>(NP, 1));
+    size_t cap1 = cap > 0 ? (size_t)cap : 1;
+    size_t np1 = NP > 0 ? (size_t)NP : 1;
+    auto A = [&](auto** ptr, size_t n) { return dalloc_n(ctx, v->allocs, v->bytes, n, ptr); };
+    if ((rc = A(&dv.px, cap1)) || (rc = A(&dv.py, cap1)) || (rc = A(&dv.pz, cap1)) || (rc = A(&dv.nx, cap1)) ||
+        (rc = A(&dv.ny, cap1)) || (rc = A(&dv.nz, cap1)) || (rc = A(&dv.ir, cap1)) || (rc = A(&dv.ig, cap1)) ||
+        (rc = A(&dv.ib, cap1)) || (rc = A(&dv.tri, cap1)) || (rc = A(&dv.count, 1)) || (rc = A(&b.pflags, np1)) ||
+        (rc = A(&b.sortbuf, (size_t)n2)) || (rc = A(&b.sorted, np1)) || (rc = A(&b.keys, np1)) ||
+        (rc = A(&b.strata, (size_t)std::max(1, p->k_near))) || (rc = A(&b.vpl_path, cap1)) ||
+        (rc = A(&b.vpl_bounce, cap1)) || (rc = A(&b.state, 1)) || (rc = A(&b.q, np1)) ||
+        (rc = A(&b.scan_out, np1 + 1)) || (rc = A(&b.stage_pos, 3 * cap1)) || (rc = A(&b.stage_flux, 3 * cap1)) ||
+        (rc = A(&b.w_count, (size_t)batch)) || (rc = A(&b.w_pos, 9 * (size_t)batch)) ||
+        (rc = A(&b.w_flux, 9 * (size_t)batch)) || (rc = A(&b.w_tri, 3 * (size_t)batch)) ||
+        (rc = A(&b.w_bounce, 3 * (size_t)batch)) || (rc = A(&b.scan_tmp, (size_t)b.scan_tmp_len))) {
+        release_set(ctx, v);
+        return rc;
+    }
+    dv.capacity = cap;
+    b.F = b.scan_out + 1;
+    CamBasis cb = cam_basis(cam);
+    GenParams gp{p->k_near, p->n_far, p->max_bounces, p->max_paths, p->d_near, p->patch_h, p->t_eps};
+    hipError_t e = launch_generate(so->dev, so->light, cb, gp, dv, b, s);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&v->done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(v->done, s);
+    if (e != hipSuccess) {
+        release_set(ctx, v);
+        return fail(VPLG_EHIP, "generation launch failed: %s", hipGetErrorString(e));
+    }
+    uint64_t id = ctx->next_id++;
+    ctx->sets[id] = v;
+    *vplset_id = id;
+    return VPLG_OK;
+}
+
+int vplg_vpls_regenerate(vplg_context* ctx, uint64_t vplset_id, const vplg_camera* cam, const vplg_gen_params* p,
+                         void* stream)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    VplSetObj* v = find_set(ctx, vplset_id);
+    if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
+    if (!v->generated) return fail(VPLG_EINVAL, "VPL set %llu was uploaded, not generated", (unsigned long long)vplset_id);
+    if ((rc = check_camera(cam)) || (rc = check_gen_params(p))) return rc;
+    if (p->k_near != v->k_near || p->n_far != v->n_far || p->patch_h != v->patch_h)
+        return fail(VPLG_EINVAL, "regeneration must keep k_near, n_far and patch_h of the set");
+    SceneObj* so = find_scene(ctx, v->scene_id);
+    if (!so) return fail(VPLG_ENOTFOUND, "the scene of VPL set %llu was released", (unsigned long long)vplset_id);
+    CamBasis cb = cam_basis(cam);
+    GenParams gp{p->k_near, p->n_far, p->max_bounces, p->max_paths, p->d_near, p->patch_h, p->t_eps};
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(launch_generate(so->dev, so->light, cb, gp, v->dev, v->gen, s));
+    HIPCHK(hipEventRecord(v->done, s));
+    return VPLG_OK;
+}
+
+int vplg_vplset_stats(vplg_context* ctx, uint64_t vplset_id, vplg_gen_stats* out)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (!out) return fail(VPLG_EINVAL, "null argument");
+    VplSetObj* v = find_set(ctx, vplset_id);
+    if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
+    if (!v->generated) return fail(VPLG_EINVAL, "VPL set %llu was uploaded, not generated", (unsigned long long)vplset_id);
+    if ((rc = wait_set(v))) return rc;
+    GenState st;
+    HIPCHK(hipMemcpy(&st, v->gen.state, sizeof st, hipMemcpyDeviceToHost));
+    out->n_patches = st.n_patches;
+    out->n_near = st.n_near;
+    out->n_eligible = st.n_eligible;
+    out->q_total = st.q_total;
+    out->k_eff = st.k_eff;
+    out->n_far_target = st.n_far_target;
+    out->n_far = st.n_far;
+    out->n_paths = st.n_paths;
+    for (int i = 0; i < 3; ++i) out->far_by_bounce[i] = st.far_b[i];
+    out->flags = st.flags;
+    out->near_discarded = st.near_discarded;
+    if (st.flags & 2) return fail(VPLG_EINVAL, "fixed-point area total too large for %d strata", v->k_near);
+    return VPLG_OK;
+}
+
+int vplg_vplset_count(vplg_context* ctx, uint64_t vplset_id, int32_t* n)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (!n) return fail(VPLG_EINVAL, "null argument");
+    VplSetObj* v = find_set(ctx, vplset_id);
+    if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
+    return set_count(v, n);
+}
+
+int vplg_vpls_upload(vplg_context* ctx, const float* pos, const float* nrm, const float* intensity,
+                     const int32_t* host_tri, int32_t n, void* stream, uint64_t* vplset_id)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (!vplset_id || n < 0 || (n > 0 && (!pos || !nrm || !intensity || !host_tri)))
+        return fail(VPLG_EINVAL, "bad VPL upload arguments");
+    if (n > (1 << 26)) return fail(VPLG_EINVAL, "too many VPLs (%d)", n);
+    hipStream_t s = (hipStream_t)stream;
+    auto* v = new VplSetObj;
+    DevVpls& dv = v->dev;
+    size_t c1 = n > 0 ? (size_t)n : 1;
+    auto A = [&](auto** ptr, size_t k) { return dalloc_n(ctx, v->allocs, v->bytes, k, ptr); };
+    if ((rc = A(&dv.px, c1)) || (rc = A(&dv.py, c1)) || (rc = A(&dv.pz, c1)) || (rc = A(&dv.nx, c1)) ||
+        (rc = A(&dv.ny, c1)) || (rc = A(&dv.nz, c1)) || (rc = A(&dv.ir, c1)) || (rc = A(&dv.ig, c1)) ||
+        (rc = A(&dv.ib, c1)) || (rc = A(&dv.tri, c1)) || (rc = A(&dv.count, 1))) {
+        release_set(ctx, v);
+        return rc;
+    }
+    dv.capacity = n;
+    std::vector<float> planes(9 * c1);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            planes[k * c1 + i] = pos[3 * i + k];
+            planes[(3 + k) * c1 + i] = nrm[3 * i + k];
+            planes[(6 + k) * c1 + i] = intensity[3 * i + k];
+        }
+    float* dst[9] = {dv.px, dv.py, dv.pz, dv.nx, dv.ny, dv.nz, dv.ir, dv.ig, dv.ib};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 9 && e == hipSuccess && n > 0; ++k)
+        e = hipMemcpyAsync(dst[k], &planes[k * c1], (size_t)n * sizeof(float), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n > 0) e = hipMemcpyAsync(dv.tri, host_tri, (size_t)n * 4, hipMemcpyHostToDevice, s);
+    int32_t cnt = n;
+    if (e == hipSuccess) e = hipMemcpyAsync(dv.count, &cnt, 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        release_set(ctx, v);
+        return fail(VPLG_EHIP, "VPL upload failed: %s", hipGetErrorString(e));
+    }
+    uint64_t id = ctx->next_id++;
+    ctx->sets[id] = v;
+    *vplset_id = id;
+    return VPLG_OK;
+}
+
+int vplg_vpls_download(vplg_context* ctx, uint64_t vplset_id, float* pos, float* nrm, float* intensity,
+                       int32_t* host_tri, int32_t cap, int32_t* n)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (!n) return fail(VPLG_EINVAL, "null count pointer");
+    VplSetObj* v = find_set(ctx, vplset_id);
+    if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
+    int32_t cnt = 0;
+    if ((rc = set_count(v, &cnt))) return rc;
+    *n = cnt;
+    if (cap < cnt) return fail(VPLG_EINVAL, "capacity %d < %d VPLs", cap, cnt);
+    if (cnt == 0) return VPLG_OK;
+    std::vector<float> tmp(9 * (size_t)cnt);
+    const DevVpls& dv = v->dev;
+    const float* src[9] = {dv.px, dv.py, dv.pz, dv.nx, dv.ny, dv.nz, dv.ir, dv.ig, dv.ib};
+    for (int k = 0; k < 9; ++k)
+        HIPCHK(hipMemcpy(&tmp[k * (size_t)cnt], src[k], (size_t)cnt * 4, hipMemcpyDeviceToHost));
+    for (int i = 0; i < cnt; ++i)
+        for (int k = 0; k < 3; ++k) {
+            if (pos) pos[3 * i + k] = tmp[k * (size_t)cnt + i];
+            if (nrm) nrm[3 * i + k] = tmp[(3 + k) * (size_t)cnt + i];
+            if (intensity) intensity[3 * i + k] = tmp[(6 + k) * (size_t)cnt + i];
+        }
+    if (host_tri) HIPCHK(hipMemcpy(host_tri, dv.tri, (size_t)cnt * 4, hipMemcpyDeviceToHost));
+    return VPLG_OK;
+}
+
+int vplg_vplset_debug(vplg_context* ctx, uint64_t vplset_id, int32_t what, void* host_buf, int64_t cap_bytes,
+                      int64_t* n_items)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (!n_items) return fail(VPLG_EINVAL, "null argument");
+    VplSetObj* v = find_set(ctx, vplset_id);
+    if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
+    if (!v->generated) return fail(VPLG_EINVAL, "VPL set was uploaded, not generated");
+    if ((rc = wait_set(v))) return rc;
+    GenState st;
+    HIPCHK(hipMemcpy(&st, v->gen.state, sizeof st, hipMemcpyDeviceToHost));
+    int32_t cnt = 0;
+    if ((rc = set_count(v, &cnt))) return rc;
+    const void* src = nullptr;
+    size_t elem = 0;
+    int64_t n = 0;
+    switch (what) {
+    case 0: src = v->gen.pflags; elem = 1; n = st.n_patches; break;
+    case 1: src = v->gen.sorted; elem = 4; n = st.n_eligible; break;
+    case 2: src = v->gen.keys; elem = 4; n = st.n_eligible; break;
+    case 3: src = v->gen.F; elem = 8; n = st.n_eligible; break;
+    case 4: src = v->gen.strata; elem = 4; n = st.k_eff; break;
+    case 5: src = v->gen.vpl_path; elem = 4; n = cnt; break;
+    case 6: src = v->gen.vpl_bounce; elem = 4; n = cnt; break;
+    case 7: src = v->gen.patch_off; elem = 8; n = v->n_tris + 1; break;
+    default: return fail(VPLG_EINVAL, "unknown debug array %d", what);
+    }
+    *n_items = n;
+    if (!host_buf || cap_bytes < (int64_t)(n * elem)) return fail(VPLG_EINVAL, "buffer too small (%lld bytes needed)",
+                                                                   (long long)(n * elem));
+    if (n > 0) HIPCHK(hipMemcpy(host_buf, src, (size_t)n * elem, hipMemcpyDeviceToHost));
+    return VPLG_OK;
+}
+
+int vplg_vplset_release(vplg_context* ctx, uint64_t vplset_id)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    VplSetObj* v = find_set(ctx, vplset_id);
+    if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
+    HIPCHK(hipDeviceSynchronize());
+    release_set(ctx, v);
+    ctx->sets.erase(vplset_id);
+    return VPLG_OK;
+}
+
+static int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                         float* const radiance[3], const vplg_gather_params* p, GatherArgs* a)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (!radiance || !p) return fail(VPLG_EINVAL, "null argument");
+    for (int c = 0; c < 3; ++c)
+        if (!radiance[c]) return fail(VPLG_EINVAL, "null radiance plane");
+    if ((rc = check_gbuffer(gb))) return rc;
+    if (!(p->g_clamp > 0.f) || !(p->t_eps >= 0.f && p->t_eps < 0.5f))
+        return fail(VPLG_EINVAL, "bad gather parameters (g_clamp %g, t_eps %g)", p->g_clamp, p->t_eps);
+    SceneObj* so = find_scene(ctx, scene_id);
+    if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
+    VplSetObj* v = find_set(ctx, vplset_id);
+    if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
+    a->scene = so->dev;
+    a->vpls = v->dev;
+    a->gb = dev_gbuffer(gb);
+    for (int c = 0; c < 3; ++c) a->out[c] = radiance[c];
+    a->g_clamp = p->g_clamp;
+    a->t_eps = p->t_eps;
+    a->counters = nullptr;
+    return VPLG_OK;
+}
+
+int vplg_gather(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                float* const radiance[3], const vplg_gather_params* p, void* stream)
+{
+    GatherArgs a;
+    int rc = gather_common(ctx, scene_id, vplset_id, gb, radiance, p, &a);
+    if (rc) return rc;
+    HIPCHK(launch_gather(a, false, (hipStream_t)stream));
+    return VPLG_OK;
+}
+
+int vplg_gather_counted(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                        float* const radiance[3], const vplg_gather_params* p, uint64_t* counters, void* stream)
+{
+    GatherArgs a;
+    int rc = gather_common(ctx, scene_id, vplset_id, gb, radiance, p, &a);
+    if (rc) return rc;
+    if (!counters) return fail(VPLG_EINVAL, "null counters");
+    a.counters = (unsigned long long*)counters;
+    HIPCHK(launch_gather(a, true, (hipStream_t)stream));
+    return VPLG_OK;
+}
+
+int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                                const int32_t* pixels, int32_t n_px, uint32_t* vis_bits, const vplg_gather_params* p,
+                                void* stream)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if ((rc = check_gbuffer(gb))) return rc;
+    if (n_px < 0 || (n_px > 0 && (!pixels || !vis_bits)) || !p) return fail(VPLG_EINVAL, "bad dump arguments");
+    SceneObj* so = find_scene(ctx, scene_id);
+    if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
+    VplSetObj* v = find_set(ctx, vplset_id);
+    if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
+    int32_t M = 0;
+    if ((rc = set_count(v, &M))) return rc;
+    VisDumpArgs a;
+    a.scene = so->dev;
+    a.vpls = v->dev;
+    a.gb = dev_gbuffer(gb);
+    a.pixels = pixels;
+    a.n_px = n_px;
+    a.words = (M + 31) / 32;
+    a.bits = vis_bits;
+    a.t_eps = p->t_eps;
+    HIPCHK(launch_vis_dump(a, (hipStream_t)stream));
+    return VPLG_OK;
+}
+
+}  // extern "C"

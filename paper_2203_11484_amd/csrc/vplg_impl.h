@@ -1,0 +1,166 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the
+// VPL library.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vplg {
+
+// ---------------------------------------------------------------------------
+// Device-resident scene
+// ---------------------------------------------------------------------------
+//
+// BVH2 with both child boxes stored in the parent (one 64-byte node = four
+// float4):
+//   n0 = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
+//   n1 = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
+//   n2 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
+//   n3 = (int c0, int c1, int c0_count, int c1_count)
+// A child with count > 0 is a leaf holding triangles [c, c + count) of the
+// leaf-ordered triangle array; count == 0 and c >= 0 is an inner node; c < 0
+// is an absent child (its box is empty).  Node 0 is the root.
+//
+// Leaf-ordered triangles, three float4 each: (A, id), (B - A, 0),
+// (C - A, cut), id = the original triangle index (bit pattern of an int) and
+// cut = (kParallelTau |(B - A) x (C - A)|)^2.  The FP32 ray tests treat a ray
+// whose direction makes an angle below kParallelTau with the triangle's plane
+// as missing it: there |det| is at the level of FP32 rounding and the
+// barycentrics are noise, and any such ray that does cross the triangle is a
+// grazing pair whose visibility either answer serves.
+constexpr double kParallelTau = 2e-5;
+constexpr int kMaxDepth = 48;   // builder guarantees depth <= kMaxDepth - 1
+constexpr int kStack = 48;      // per-lane traversal stack entries
+
+struct DevScene {
+    int n_tris = 0;
+    int n_nodes = 0;
+    const float4* nodes = nullptr;    // 4 per node
+    const float4* tris = nullptr;     // 3 per leaf-ordered triangle
+    const float* xyz = nullptr;       // original [T][3][3] float32
+    const float* albedo = nullptr;    // [T][3]
+    const uint8_t* flags = nullptr;   // [T]
+    const float4* normals = nullptr;  // [T] unit face normal (float32 of the FP64 value)
+    float lo[3], hi[3];               // scene bounding box (unpadded)
+};
+
+struct DevLight {
+    int kind;  // 0 point, 1 quad
+    float pos[3], eu[3], ev[3], power[3];
+};
+
+// VPL set in structure-of-arrays form; count on the device for generated sets.
+struct DevVpls {
+    float* px = nullptr; float* py = nullptr; float* pz = nullptr;
+    float* nx = nullptr; float* ny = nullptr; float* nz = nullptr;
+    float* ir = nullptr; float* ig = nullptr; float* ib = nullptr;
+    int32_t* tri = nullptr;
+    int32_t* count = nullptr;  // device int32: number of valid VPLs
+    int capacity = 0;
+};
+
+struct DevGBuffer {
+    const float* pos[3];
+    const float* nrm[3];
+    const float* alb[3];
+    const int32_t* tri;
+    int width, height;
+};
+
+struct GatherArgs {
+    DevScene scene;
+    DevVpls vpls;
+    DevGBuffer gb;
+    float* out[3];
+    float g_clamp;
+    float t_eps;
+    unsigned long long* counters;  // instrumented variant only
+};
+
+struct VisDumpArgs {
+    DevScene scene;
+    DevVpls vpls;
+    DevGBuffer gb;
+    const int32_t* pixels;
+    int n_px;
+    int words;  // ceil(capacity / 32)
+    uint32_t* bits;
+    float t_eps;
+};
+
+struct GBufferArgs {
+    DevScene scene;
+    float eye[3], f[3], r[3], u[3];
+    float th, tx;
+    float* pos[3];
+    float* nrm[3];
+    float* alb[3];
+    int32_t* tri;
+    int width, height;
+};
+
+// Camera basis in FP64 (host-computed, shared by the near test of generation).
+struct CamBasis {
+    double eye[3], f[3], r[3], u[3];
+    double th, tx;  // tan(vfov / 2) and th * W / H
+    int width, height;
+};
+
+struct GenParams {
+    int k_near, n_far, max_bounces, max_paths;
+    double d_near, patch_h, t_eps;
+};
+
+// Device-side record of one generation (counts are int64).
+struct GenState {
+    long long n_patches, n_near, n_eligible, q_total, k_eff, n_far_target, n_far, n_paths;
+    long long far_b[3];
+    long long flags, near_discarded;
+    int walk_done;
+    int pad;
+};
+
+// Buffers of one generation.
+struct GenBuffers {
+    int n_patches;          // host-known total
+    int32_t* level;         // [T] refinement level of each triangle
+    long long* patch_off;   // [T + 1]
+    uint8_t* pflags;        // [n_patches]
+    unsigned long long* sortbuf;  // [pow2 >= n_patches] (key << 32 | patch)
+    int32_t* sorted;        // [n_patches]
+    uint32_t* keys;         // [n_patches]
+    long long* F;           // [n_patches]
+    int32_t* strata;        // [k_near]
+    int32_t* vpl_path;      // [capacity]
+    int32_t* vpl_bounce;    // [capacity]
+    GenState* state;        // device
+    long long* q;           // [n_patches] fixed-point areas in sorted order
+    long long* scan_out;    // [n_patches + 1] exclusive prefix of q (F = scan_out + 1)
+    double* stage_pos;      // [capacity][3] VPL positions before rounding to float
+    double* stage_flux;     // [capacity][3] walk fluxes before normalisation
+    // walk scratch for one batch of paths
+    int batch;              // capacity in paths
+    int32_t* w_count;       // [batch] far deposits | discard mask << 8
+    double* w_pos;          // [batch][3][3]
+    double* w_flux;         // [batch][3][3]
+    int32_t* w_tri;         // [batch][3]
+    int32_t* w_bounce;      // [batch][3]
+    long long* scan_tmp;    // scan scratch
+    int scan_tmp_len;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+hipError_t launch_gather(const GatherArgs& a, bool counted, hipStream_t s);
+hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s);
+hipError_t launch_gbuffer(const GBufferArgs& a, hipStream_t s);
+
+hipError_t launch_patch_levels(const DevScene& sc, double h, int32_t* level, long long* counts, hipStream_t s);
+hipError_t launch_scan_i64(const long long* in, long long* out, int n, long long* tmp, int tmp_len,
+                           hipStream_t s);  // exclusive scan, out[n] = total
+int scan_tmp_needed(int n);
+hipError_t launch_generate(const DevScene& sc, const DevLight& L, const CamBasis& cam, const GenParams& p,
+                           const DevVpls& v, const GenBuffers& b, hipStream_t s);
+
+}  // namespace vplg

@@ -182,8 +182,10 @@ def quad_light(corner, edge_u, edge_v, power):
 
 def default_params(**kw):
     p = dict(k_near=64, n_far=192, max_bounces=3, d_near=1.8, patch_h=0.1,
-             g_clamp=10.0, t_eps=1e-4, max_paths=1 << 20)
+             g_clamp=10.0, t_eps=1e-4)
     p.update(kw)
+    # cap on walk paths: 64 per VPL of the budget (reaching it is flagged)
+    p.setdefault("max_paths", 64 * (p["k_near"] + p["n_far"]) + 1024)
     return p
 
 
