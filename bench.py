@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--workload", default="room20k")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile-vpl", type=int, default=0, help="waves (VPL slices) per 8x8 pixel tile, 0 = default")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -94,6 +95,7 @@ def main():
     vid = vplg.vpls_generate(ctx, sid, cam, prm, stream)
     M = vplg.vplset_count(ctx, vid)
     gp = vplg.make_gather_params(prm)
+    gp.tile_vpl = args.tile_vpl
 
     def step(ev=None):
         vplg.gbuffer_render(ctx, sid, cam, gb, stream)

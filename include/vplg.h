@@ -209,7 +209,8 @@ int vplg_vplset_release(vplg_context* ctx, uint64_t vplset_id);
 
 /* g_clamp: C in min(C, cos_p cos_k / r^2) (> 0).  t_eps: shadow segments
  * x + s (y - x) test s in (t_eps, 1 - t_eps), both host triangles excluded.
- * tile_px, tile_vpl: 0 = library default. */
+ * tile_px: pixels per tile, 0 or 64 (8 x 8).  tile_vpl: waves sharing one
+ * tile, each taking every tile_vpl-th VPL: 0 (= 8) or 1, 2, 4, 8, 16. */
 typedef struct {
     float g_clamp, t_eps;
     int32_t tile_px, tile_vpl;

@@ -3,17 +3,26 @@
 //
 // Every shadow ray is the segment x + s (y - x), s in (t_eps, 1 - t_eps),
 // tested against the BVH with both host triangles excluded; occlusion is
-// two-sided and emitters occlude.  Traversal stacks live in LDS, one column
-// per lane (entry i of lane l at [i * BLOCK + l]: consecutive lanes hit
-// consecutive banks).
+// two-sided and emitters occlude.
+//
+// Shadow rays are traced as wave64 packets: a wave owns an 8 x 8 pixel tile
+// and all 64 rays run to the same VPL, so they are coherent.  The wave walks
+// the BVH together with uniform control flow: node and triangle records are
+// wave-uniform loads (scalar unit, SGPRs), each lane tests its own ray, and
+// ballots decide which children the packet enters.  The traversal stack is
+// wave-uniform and lives in one VGPR across the lanes (entry i in lane i:
+// push by lane select, pop by v_readlane), so it costs no LDS at all.
 #include "vplg_impl.h"
 
 namespace vplg {
 
 namespace {
 
-constexpr int BLOCK = 256;     // 4 wave64 per workgroup
-constexpr int TILE_V = 256;    // VPLs staged in LDS per tile
+constexpr int BLOCK = 256;              // 4 wave64 per workgroup (G-buffer, dump)
+constexpr int kGatherMaxWaves = 16;     // waves per gather workgroup (VPL slices of one tile)
+constexpr int kGatherMaxThreads = 64 * kGatherMaxWaves;
+constexpr int kChunk = 16;              // VPLs per first-level partial sum of a wave
+constexpr int kXcds = 8;                // MI355X: 8 accelerator complex dies, one L2 each
 constexpr float kInvPi = 0.318309886183790671538f;
 
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -78,10 +87,15 @@ __device__ __forceinline__ void child_boxes(const float4& n0, const float4& n1, 
     *hi1 = fminf(fminf(fmaxf(d0, d1), fmaxf(e0, e1)), fminf(fmaxf(f0, f1), thi));
 }
 
-// Any hit on the segment o + s d, s in (tlo, thi), skipping triangles ex0/ex1.
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Any-hit test of a wave's 64 segments o + s d, s in (tlo, thi), walked as
+// one packet.  `act` marks the lanes with a ray; ex0 (per lane) and ex1
+// (wave-uniform) are the excluded host triangles.  Returns, per lane,
+// whether its ray is active and unblocked.
 template <bool COUNT>
-__device__ bool occluded(const DevScene& sc, float ox, float oy, float oz, float dx, float dy, float dz, float tlo,
-                         float thi, int ex0, int ex1, int* __restrict__ stack, Counters& cnt)
+__device__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz, float dx, float dy, float dz,
+                               bool act, float tlo, float thi, int ex0, int ex1, int lane, Counters& cnt)
 {
     SlabRay r;
     r.ix = safe_inv(dx);
@@ -93,53 +107,68 @@ __device__ bool occluded(const DevScene& sc, float ox, float oy, float oz, float
     const float d2 = dx * dx + dy * dy + dz * dz;
     const float4* __restrict__ nodes = sc.nodes;
     const float4* __restrict__ tris = sc.tris;
+    bool alive = act;
+    int slot = 0;  // stack entry `lane` of the wave-uniform stack
     int sp = 0;
     int node = 0;
     while (true) {
-        float4 n0 = nodes[4 * node];
-        float4 n1 = nodes[4 * node + 1];
-        float4 n2 = nodes[4 * node + 2];
-        float4 n3f = nodes[4 * node + 3];
+        const float4* nd = nodes + 4 * node;
+        float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3f = nd[3];
         int c0 = __float_as_int(n3f.x), c1 = __float_as_int(n3f.y);
         int k0 = __float_as_int(n3f.z), k1 = __float_as_int(n3f.w);
-        if (COUNT) cnt.nodes++;
+        if (COUNT && alive) cnt.nodes++;
         float lo0, hi0, lo1, hi1;
         child_boxes(n0, n1, n2, r, tlo, thi, &lo0, &hi0, &lo1, &hi1);
-        bool h0 = lo0 <= hi0 && c0 >= 0;
-        bool h1 = lo1 <= hi1 && c1 >= 0;
-        if (h0 && k0 > 0) {
-            for (int i = c0; i < c0 + k0; ++i) {
-                float t, u, v;
-                int id;
-                if (COUNT) cnt.tris++;
-                if (tri_hit32(tris, i, ox, oy, oz, dx, dy, dz, d2, tlo, thi, ex0, ex1, &t, &u, &v, &id)) return true;
+        bool h0 = alive && lo0 <= hi0 && c0 >= 0;
+        bool h1 = alive && lo1 <= hi1 && c1 >= 0;
+        unsigned long long b0 = ballot(h0), b1 = ballot(h1);
+        if (k0 > 0) {
+            if (b0) {
+                for (int i = c0; i < c0 + k0; ++i) {
+                    float t, u, v;
+                    int id;
+                    if (COUNT && h0 && alive) cnt.tris++;
+                    bool hit = tri_hit32(tris, i, ox, oy, oz, dx, dy, dz, d2, tlo, thi, ex0, ex1, &t, &u, &v, &id);
+                    if (h0 && hit) alive = false;
+                }
             }
             h0 = false;
         }
-        if (h1 && k1 > 0) {
-            for (int i = c1; i < c1 + k1; ++i) {
-                float t, u, v;
-                int id;
-                if (COUNT) cnt.tris++;
-                if (tri_hit32(tris, i, ox, oy, oz, dx, dy, dz, d2, tlo, thi, ex0, ex1, &t, &u, &v, &id)) return true;
+        if (k1 > 0) {
+            if (b1) {
+                for (int i = c1; i < c1 + k1; ++i) {
+                    float t, u, v;
+                    int id;
+                    if (COUNT && h1 && alive) cnt.tris++;
+                    bool hit = tri_hit32(tris, i, ox, oy, oz, dx, dy, dz, d2, tlo, thi, ex0, ex1, &t, &u, &v, &id);
+                    if (h1 && hit) alive = false;
+                }
             }
             h1 = false;
         }
-        if (h0 && h1) {
-            bool near0 = lo0 <= lo1;
-            stack[sp * BLOCK] = near0 ? c1 : c0;
+        unsigned long long live = ballot(alive);
+        if (live == 0) return false;
+        b0 = ballot(h0 && alive);
+        b1 = ballot(h1 && alive);
+        if (b0 && b1) {
+            // near child first, as seen by the lowest lane that enters both
+            int l = __builtin_ctzll(b0 & b1 ? (b0 & b1) : live);
+            bool first0 = __builtin_amdgcn_readlane(lo0 <= lo1 ? 1 : 0, l) != 0;
+            int far_c = first0 ? c1 : c0;
+            slot = lane == sp ? far_c : slot;
             ++sp;
-            node = near0 ? c0 : c1;
-        } else if (h0) {
+            node = first0 ? c0 : c1;
+        } else if (b0) {
             node = c0;
-        } else if (h1) {
+        } else if (b1) {
             node = c1;
         } else {
-            if (sp == 0) return false;
+            if (sp == 0) break;
             --sp;
-            node = stack[sp * BLOCK];
+            node = __builtin_amdgcn_readlane(slot, sp);
         }
     }
+    return alive;
 }
 
 // Pixel of lane `tid` in a 16 x 16 tile: each wave64 owns an 8 x 8 quadrant.
@@ -150,15 +179,35 @@ __device__ __forceinline__ void tile_pixel(int tid, int bx, int by, int* px, int
     *py = by * 16 + (w >> 1) * 8 + (lane >> 3);
 }
 
-template <bool COUNT>
-__global__ __launch_bounds__(BLOCK) void k_gather(GatherArgs a)
+// Logical tile of a workgroup.  Workgroups are dealt to the 8 XCDs round
+// robin; renumbering them so that each XCD gets one contiguous band of tiles
+// keeps the rays of neighbouring tiles, and the BVH nodes they touch, in the
+// same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n)
 {
-    __shared__ float s_v[10][TILE_V];
-    __shared__ int s_stack[kStack * BLOCK];
-    const int tid = threadIdx.x;
-    int px, py;
-    tile_pixel(tid, blockIdx.x, blockIdx.y, &px, &py);
+    const int per = (n + kXcds - 1) / kXcds;
+    const int xcd = b % kXcds, idx = b / kXcds;
+    const int full = n - (per - 1) * kXcds;  // XCDs that own `per` tiles (the rest own per - 1)
+    int t = xcd < full ? xcd * per + idx : full * per + (xcd - full) * (per - 1) + idx;
+    return t;
+}
+
+// One workgroup per 8 x 8 pixel tile; its waves split the VPLs (wave w takes
+// k = w, w + nw, ...), each wave tracing its shadow rays as one packet.  Per
+// wave the terms are summed in chunks of kChunk VPLs, chunk sums are added in
+// order, and the waves' sums are added in wave order: deterministic.
+template <bool COUNT>
+__global__ __launch_bounds__(kGatherMaxThreads) void k_gather(GatherArgs a)
+{
+    __shared__ float s_red[kGatherMaxWaves][3][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
     const int W = a.gb.width, H = a.gb.height;
+    const int tiles_x = (W + 7) >> 3, tiles_y = (H + 7) >> 3;
+    const int tile = xcd_tile(blockIdx.x, tiles_x * tiles_y);
+    const int px = (tile % tiles_x) * 8 + (lane & 7);
+    const int py = (tile / tiles_x) * 8 + (lane >> 3);
     const bool valid = px < W && py < H;
     const int p = py * W + px;
     float x = 0, y = 0, z = 0, nx = 0, ny = 0, nz = 0;
@@ -172,91 +221,97 @@ __global__ __launch_bounds__(BLOCK) void k_gather(GatherArgs a)
     const int M = *a.vpls.count;
     const float C = a.g_clamp;
     const float tlo = a.t_eps, thi = 1.0f - a.t_eps;
-    int* stack = s_stack + tid;
+    const float4* __restrict__ vp = a.vpls.pack;
     Counters cnt;
     unsigned long long pairs = 0;
     float ar = 0.f, ag = 0.f, ab = 0.f;
-    for (int base = 0; base < M; base += TILE_V) {
-        __syncthreads();
-        int j = base + tid;
-        if (j < M) {
-            s_v[0][tid] = a.vpls.px[j]; s_v[1][tid] = a.vpls.py[j]; s_v[2][tid] = a.vpls.pz[j];
-            s_v[3][tid] = a.vpls.nx[j]; s_v[4][tid] = a.vpls.ny[j]; s_v[5][tid] = a.vpls.nz[j];
-            s_v[6][tid] = a.vpls.ir[j]; s_v[7][tid] = a.vpls.ig[j]; s_v[8][tid] = a.vpls.ib[j];
-            s_v[9][tid] = __int_as_float(a.vpls.tri[j]);
-        }
-        __syncthreads();
-        const int nt = min(TILE_V, M - base);
-        float pr = 0.f, pg = 0.f, pb = 0.f;
-        if (active) {
-            if (COUNT) pairs += nt;
-            for (int k = 0; k < nt; ++k) {
-                float dx = s_v[0][k] - x, dy = s_v[1][k] - y, dz = s_v[2][k] - z;
+    if (ballot(active) != 0) {
+        for (int base = wave; base < M; base += nw * kChunk) {
+            float pr = 0.f, pg = 0.f, pb = 0.f;
+            for (int j = 0; j < kChunk; ++j) {
+                const int k = base + j * nw;
+                if (k >= M) break;
+                if (COUNT && active) pairs++;
+                float4 v0 = vp[3 * k], v1 = vp[3 * k + 1];
+                float dx = v0.x - x, dy = v0.y - y, dz = v0.z - z;
                 float cp = nx * dx + ny * dy + nz * dz;
-                float ck = -(s_v[3][k] * dx + s_v[4][k] * dy + s_v[5][k] * dz);
-                if (cp > 0.f && ck > 0.f) {
-                    float r2 = dx * dx + dy * dy + dz * dz;
-                    float g = fminf(C, cp * ck * rcpf(r2 * r2));
-                    if (COUNT) cnt.rays++;
-                    if (!occluded<COUNT>(a.scene, x, y, z, dx, dy, dz, tlo, thi, tp, __float_as_int(s_v[9][k]), stack,
-                                         cnt)) {
-                        pr = fmaf(s_v[6][k], g, pr);
-                        pg = fmaf(s_v[7][k], g, pg);
-                        pb = fmaf(s_v[8][k], g, pb);
-                    }
+                float ck = -(v1.x * dx + v1.y * dy + v1.z * dz);
+                bool act = active && cp > 0.f && ck > 0.f;
+                if (ballot(act) == 0) continue;
+                if (COUNT && act) cnt.rays++;
+                float r2 = dx * dx + dy * dy + dz * dz;
+                float g = fminf(C, cp * ck * rcpf(r2 * r2));
+                bool vis = packet_visible<COUNT>(a.scene, x, y, z, dx, dy, dz, act, tlo, thi, tp, __float_as_int(v0.w),
+                                                 lane, cnt);
+                if (vis) {
+                    float4 v2 = vp[3 * k + 2];
+                    pr = fmaf(v2.x, g, pr);
+                    pg = fmaf(v2.y, g, pg);
+                    pb = fmaf(v2.z, g, pb);
                 }
             }
+            ar += pr;
+            ag += pg;
+            ab += pb;
         }
-        ar += pr;
-        ag += pg;
-        ab += pb;
     }
-    if (valid) {
-        float s = kInvPi;
-        a.out[0][p] = active ? a.gb.alb[0][p] * s * ar : 0.f;
-        a.out[1][p] = active ? a.gb.alb[1][p] * s * ag : 0.f;
-        a.out[2][p] = active ? a.gb.alb[2][p] * s * ab : 0.f;
+    s_red[wave][0][lane] = ar;
+    s_red[wave][1][lane] = ag;
+    s_red[wave][2][lane] = ab;
+    __syncthreads();
+    if (wave == 0 && valid) {
+        float sr = 0.f, sg = 0.f, sb = 0.f;
+        for (int w = 0; w < nw; ++w) {
+            sr += s_red[w][0][lane];
+            sg += s_red[w][1][lane];
+            sb += s_red[w][2][lane];
+        }
+        const float s = kInvPi;
+        a.out[0][p] = active ? a.gb.alb[0][p] * s * sr : 0.f;
+        a.out[1][p] = active ? a.gb.alb[1][p] * s * sg : 0.f;
+        a.out[2][p] = active ? a.gb.alb[2][p] * s * sb : 0.f;
     }
     if (COUNT) {
         unsigned long long v[4] = {pairs, cnt.rays, cnt.nodes, cnt.tris};
         for (int c = 0; c < 4; ++c) {
-            unsigned long long s = v[c];
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-            if ((tid & 63) == 0) atomicAdd(&a.counters[c], s);
+            unsigned long long sum = v[c];
+            for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+            if (lane == 0) atomicAdd(&a.counters[c], sum);
         }
     }
 }
 
-// One thread per (pixel, 32-VPL word): bit k of the word = V(x_p, y_k),
-// evaluated for every pair with the gather's shadow-ray code.
+// One lane per listed pixel; a wave walks the VPLs and records, per lane,
+// bit k % 32 of word k / 32 = V(x_p, y_k) for every pair (no geometry-term
+// culling), with the gather's own packet traversal.
 __global__ __launch_bounds__(BLOCK) void k_vis_dump(VisDumpArgs a)
 {
-    __shared__ int s_stack[kStack * BLOCK];
     const int gid = blockIdx.x * BLOCK + threadIdx.x;
-    const int total = a.n_px * a.words;
-    if (gid >= total) return;
-    const int i = gid / a.words, w = gid % a.words;
-    const int p = a.pixels[i];
+    const int lane = threadIdx.x & 63;
+    const bool in = gid < a.n_px;
+    int p = in ? a.pixels[gid] : -1;
+    if (p >= a.gb.width * a.gb.height) p = -1;  // the pixel list lives on the device: checked here
+    const int tp = p >= 0 ? a.gb.tri[p] : -1;
+    const bool ok = p >= 0 && tp >= 0;
+    float x = 0, y = 0, z = 0;
+    if (ok) { x = a.gb.pos[0][p]; y = a.gb.pos[1][p]; z = a.gb.pos[2][p]; }
     const int M = *a.vpls.count;
-    if (p < 0 || p >= a.gb.width * a.gb.height) {  // pixel list lives on the device: check it here
-        a.bits[(size_t)i * a.words + w] = 0u;
-        return;
-    }
-    const int tp = a.gb.tri[p];
-    uint32_t bits = 0;
+    const float4* __restrict__ vp = a.vpls.pack;
     Counters cnt;
-    if (tp >= 0) {
-        float x = a.gb.pos[0][p], y = a.gb.pos[1][p], z = a.gb.pos[2][p];
+    for (int w = 0; w < a.words; ++w) {
+        uint32_t bits = 0;
         for (int b = 0; b < 32; ++b) {
             int k = w * 32 + b;
             if (k >= M) break;
-            float dx = a.vpls.px[k] - x, dy = a.vpls.py[k] - y, dz = a.vpls.pz[k] - z;
-            bool occ = occluded<false>(a.scene, x, y, z, dx, dy, dz, a.t_eps, 1.0f - a.t_eps, tp, a.vpls.tri[k],
-                                       s_stack + threadIdx.x, cnt);
-            if (!occ) bits |= 1u << b;
+            float4 v0 = vp[3 * k];
+            bool vis = false;
+            if (ballot(ok) != 0)
+                vis = packet_visible<false>(a.scene, x, y, z, v0.x - x, v0.y - y, v0.z - z, ok, a.t_eps,
+                                            1.0f - a.t_eps, tp, __float_as_int(v0.w), lane, cnt);
+            if (vis) bits |= 1u << b;
         }
+        if (in) a.bits[(size_t)gid * a.words + w] = bits;
     }
-    a.bits[(size_t)i * a.words + w] = bits;
 }
 
 // Closest hit, t in (0, inf); ties go to the smaller original triangle index.
@@ -349,23 +404,42 @@ __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
     a.alb[2][p] = a.scene.albedo[3 * bid + 2];
 }
 
+// Interleave the SoA planes of a VPL set into the gather layout.
+__global__ void k_pack_vpls(DevVpls v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *v.count || i >= v.capacity) return;
+    v.pack[3 * i] = make_float4(v.px[i], v.py[i], v.pz[i], __int_as_float(v.tri[i]));
+    v.pack[3 * i + 1] = make_float4(v.nx[i], v.ny[i], v.nz[i], 0.f);
+    v.pack[3 * i + 2] = make_float4(v.ir[i], v.ig[i], v.ib[i], 0.f);
+}
+
 }  // namespace
+
+hipError_t launch_pack_vpls(const DevVpls& v, hipStream_t s)
+{
+    if (v.capacity == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_vpls, dim3((v.capacity + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_gather(const GatherArgs& a, bool counted, hipStream_t s)
 {
-    dim3 grid((a.gb.width + 15) / 16, (a.gb.height + 15) / 16);
+    const int tiles = ((a.gb.width + 7) / 8) * ((a.gb.height + 7) / 8);
+    int waves = a.waves_per_tile;
+    if (waves < 1 || waves > kGatherMaxWaves || (waves & (waves - 1))) return hipErrorInvalidValue;
+    dim3 grid(tiles), block(64 * waves);
     if (counted)
-        hipLaunchKernelGGL(k_gather<true>, grid, dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_gather<true>, grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL(k_gather<false>, grid, dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_gather<false>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s)
 {
-    long long total = (long long)a.n_px * a.words;
-    if (total == 0) return hipSuccess;
-    dim3 grid((unsigned)((total + BLOCK - 1) / BLOCK));
+    if (a.n_px == 0 || a.words == 0) return hipSuccess;
+    dim3 grid((unsigned)((a.n_px + BLOCK - 1) / BLOCK));
     hipLaunchKernelGGL(k_vis_dump, grid, dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }

@@ -516,7 +516,8 @@ int vplg_vpls_generate(vplg_context* ctx, uint64_t scene_id, const vplg_camera* 
     auto A = [&](auto** ptr, size_t n) { return dalloc_n(ctx, v->allocs, v->bytes, n, ptr); };
     if ((rc = A(&dv.px, cap1)) || (rc = A(&dv.py, cap1)) || (rc = A(&dv.pz, cap1)) || (rc = A(&dv.nx, cap1)) ||
         (rc = A(&dv.ny, cap1)) || (rc = A(&dv.nz, cap1)) || (rc = A(&dv.ir, cap1)) || (rc = A(&dv.ig, cap1)) ||
-        (rc = A(&dv.ib, cap1)) || (rc = A(&dv.tri, cap1)) || (rc = A(&dv.count, 1)) || (rc = A(&b.pflags, np1)) ||
+        (rc = A(&dv.ib, cap1)) || (rc = A(&dv.tri, cap1)) || (rc = A(&dv.count, 1)) || (rc = A(&dv.pack, 3 * cap1)) ||
+        (rc = A(&b.pflags, np1)) ||
         (rc = A(&b.sortbuf, (size_t)n2)) || (rc = A(&b.sorted, np1)) || (rc = A(&b.keys, np1)) ||
         (rc = A(&b.strata, (size_t)std::max(1, p->k_near))) || (rc = A(&b.vpl_path, cap1)) ||
         (rc = A(&b.vpl_bounce, cap1)) || (rc = A(&b.state, 1)) || (rc = A(&b.q, np1)) ||
@@ -532,6 +533,7 @@ int vplg_vpls_generate(vplg_context* ctx, uint64_t scene_id, const vplg_camera* 
     CamBasis cb = cam_basis(cam);
     GenParams gp{p->k_near, p->n_far, p->max_bounces, p->max_paths, p->d_near, p->patch_h, p->t_eps};
     hipError_t e = launch_generate(so->dev, so->light, cb, gp, dv, b, s);
+    if (e == hipSuccess) e = launch_pack_vpls(dv, s);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&v->done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(v->done, s);
     if (e != hipSuccess) {
@@ -561,6 +563,7 @@ int vplg_vpls_regenerate(vplg_context* ctx, uint64_t vplset_id, const vplg_camer
     GenParams gp{p->k_near, p->n_far, p->max_bounces, p->max_paths, p->d_near, p->patch_h, p->t_eps};
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(launch_generate(so->dev, so->light, cb, gp, v->dev, v->gen, s));
+    HIPCHK(launch_pack_vpls(v->dev, s));
     HIPCHK(hipEventRecord(v->done, s));
     return VPLG_OK;
 }
@@ -616,7 +619,7 @@ int vplg_vpls_upload(vplg_context* ctx, const float* pos, const float* nrm, cons
     auto A = [&](auto** ptr, size_t k) { return dalloc_n(ctx, v->allocs, v->bytes, k, ptr); };
     if ((rc = A(&dv.px, c1)) || (rc = A(&dv.py, c1)) || (rc = A(&dv.pz, c1)) || (rc = A(&dv.nx, c1)) ||
         (rc = A(&dv.ny, c1)) || (rc = A(&dv.nz, c1)) || (rc = A(&dv.ir, c1)) || (rc = A(&dv.ig, c1)) ||
-        (rc = A(&dv.ib, c1)) || (rc = A(&dv.tri, c1)) || (rc = A(&dv.count, 1))) {
+        (rc = A(&dv.ib, c1)) || (rc = A(&dv.tri, c1)) || (rc = A(&dv.count, 1)) || (rc = A(&dv.pack, 3 * c1))) {
         release_set(ctx, v);
         return rc;
     }
@@ -635,6 +638,7 @@ int vplg_vpls_upload(vplg_context* ctx, const float* pos, const float* nrm, cons
     if (e == hipSuccess && n > 0) e = hipMemcpyAsync(dv.tri, host_tri, (size_t)n * 4, hipMemcpyHostToDevice, s);
     int32_t cnt = n;
     if (e == hipSuccess) e = hipMemcpyAsync(dv.count, &cnt, 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_pack_vpls(dv, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         release_set(ctx, v);
@@ -743,6 +747,12 @@ static int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_i
     a->g_clamp = p->g_clamp;
     a->t_eps = p->t_eps;
     a->counters = nullptr;
+    // tile_vpl: waves (VPL slices) per 8 x 8 tile; 0 = 8
+    int w = p->tile_vpl == 0 ? 8 : p->tile_vpl;
+    if (w < 1 || w > 16 || (w & (w - 1)))
+        return fail(VPLG_EINVAL, "tile_vpl must be 0 or a power of two in [1, 16] (got %d)", p->tile_vpl);
+    if (p->tile_px != 0 && p->tile_px != 64) return fail(VPLG_EINVAL, "tile_px must be 0 or 64 (8 x 8 pixels)");
+    a->waves_per_tile = w;
     return VPLG_OK;
 }
 

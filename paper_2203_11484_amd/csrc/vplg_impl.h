@@ -56,6 +56,8 @@ struct DevVpls {
     float* ir = nullptr; float* ig = nullptr; float* ib = nullptr;
     int32_t* tri = nullptr;
     int32_t* count = nullptr;  // device int32: number of valid VPLs
+    // gather layout: three float4 per VPL, (pos, tri bits), (nrm, 0), (I, 0)
+    float4* pack = nullptr;
     int capacity = 0;
 };
 
@@ -74,6 +76,7 @@ struct GatherArgs {
     float* out[3];
     float g_clamp;
     float t_eps;
+    int waves_per_tile;            // VPL slices per 8 x 8 pixel tile: 1, 2, 4, 8 or 16
     unsigned long long* counters;  // instrumented variant only
 };
 
@@ -155,6 +158,7 @@ struct GenBuffers {
 hipError_t launch_gather(const GatherArgs& a, bool counted, hipStream_t s);
 hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s);
 hipError_t launch_gbuffer(const GBufferArgs& a, hipStream_t s);
+hipError_t launch_pack_vpls(const DevVpls& v, hipStream_t s);
 
 hipError_t launch_patch_levels(const DevScene& sc, double h, int32_t* level, long long* counts, hipStream_t s);
 hipError_t launch_scan_i64(const long long* in, long long* out, int n, long long* tmp, int tmp_len,
