@@ -26,6 +26,20 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published)
 FLOP_PAIR, FLOP_RAY, FLOP_NODE, FLOP_TRI = 27, 6, 24, 44
 
 
+def measured_traffic(workload):
+    """HBM bytes per gather launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, scaled by
+    the same counters' reading of a 1 GiB copy; None unless the gather source is the one measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_gather_{workload}_hbm.json")
+    src = os.path.join(ROOT, "paper_2203_11484_amd", "csrc", "k_gather.hip")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != d.get("kernel_source_sha256"):
+        return None
+    return d["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(sc, target_s, seed=0):
     """The FP64 oracle's gather timed on the host cores on a bounded pixel sample of the workload."""
     import numpy as np
@@ -167,7 +181,7 @@ def main():
                    "vpls": M, "near_vpls": int(stats["k_eff"]), "far_vpls": int(stats["n_far"]),
                    "light": "point" if sc["light"]["kind"] == 0 else "quad", "g_clamp": prm["g_clamp"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_gather", "flop_per_launch": flops, "gather_ms": float(gather_ms.mean())},
         "gather_pairs_per_s": pairs_step / g_mean_s,
         "p50_frame_ms": float(np.percentile(frame_ms, 50)),
