@@ -145,10 +145,10 @@ def main():
           file=sys.stderr, flush=True)
 
     # instrumented launch (untimed): pairs, shadow rays, BVH nodes, triangle tests
-    cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(8, dtype=torch.int64, device="cuda")
     vplg.gather_counted(ctx, sid, vid, gb, rad, cnt, gp, stream)
     torch.cuda.synchronize()
-    pairs_c, rays, nodes, tris = (int(x) for x in cnt.cpu().tolist())
+    pairs_c, rays, nodes, tris, packets, psteps, plane, ptris = (int(x) for x in cnt.cpu().tolist())
     stats = vplg.vplset_stats(ctx, vid)
     valid = int((gb.tri >= 0).sum().item())
 
@@ -191,6 +191,9 @@ def main():
         "nodes_per_ray": nodes / max(rays, 1),
         "tris_per_ray": tris / max(rays, 1),
         "ray_tri_tests_per_s": tris / g_mean_s,
+        "packets": {"count": packets, "lanes_per_packet": plane / max(packets, 1),
+                    "steps_per_packet": psteps / max(packets, 1), "tri_steps_per_packet": ptris / max(packets, 1),
+                    "lane_efficiency_nodes": nodes / max(64 * psteps, 1)},
         "generation": {k: int(stats[k]) for k in ("n_patches", "n_near", "n_eligible", "n_paths")},
     }
     if not args.no_cpu:

@@ -224,9 +224,11 @@ typedef struct {
 int vplg_gather(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                 float* const radiance[3], const vplg_gather_params* p, void* stream);
 
-/* The same kernel, instrumented: also adds to counters[0..3] (device uint64)
- * the pairs evaluated, shadow rays cast, BVH nodes visited and ray-triangle
- * tests performed.  For measurement; slower than vplg_gather. */
+/* The same kernel, instrumented: also adds to counters[0..7] (device uint64)
+ * the pairs evaluated, shadow rays cast, BVH node visits and ray-triangle
+ * tests of active lanes, then, per wave, packets traced, packet node steps,
+ * active lanes at packet start and packet triangle steps.  For measurement;
+ * slower than vplg_gather. */
 int vplg_gather_counted(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                         float* const radiance[3], const vplg_gather_params* p, uint64_t* counters, void* stream);
 
@@ -237,6 +239,44 @@ int vplg_gather_counted(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id
 int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                                 const int32_t* pixels, int32_t n_px, uint32_t* vis_bits,
                                 const vplg_gather_params* p, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched gather and tile autotuning                                       */
+/* ------------------------------------------------------------------------ */
+
+/* One view of a batch: a resident scene and VPL set, its G-buffer, its
+ * radiance planes and gather parameters (params.tile_vpl 0 = the autotuned
+ * choice for the view's shape; a batch accepts 1, 2, 4 or 8). */
+typedef struct {
+    uint64_t scene_id, vplset_id;
+    vplg_gbuffer gb;
+    float* radiance[3];
+    vplg_gather_params params;
+} vplg_view;
+
+/* Gather n_views views of any scenes, resolutions and VPL counts in one
+ * persistent launch (at most 4096 views).  Workgroups pull (view, tile group)
+ * items from a device counter, most expensive views first.  The launch is a
+ * HIP graph captured once per context and replayed; each call only rewrites
+ * the device work table (copied from pinned host staging on `stream`) before
+ * the replay.  Every view's radiance is identical to vplg_gather's with the
+ * same tile_vpl, whatever else is in the batch.  Calls on one context must
+ * not overlap (they share the work table); the call waits only for the
+ * previous call's table copy. */
+int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views, void* stream);
+
+/* Time vplg_gather with tile_vpl 1, 2, 4 and 8 on this view (synchronises
+ * `stream`), remember the fastest for the view's shape bucket
+ * (ceil(log2(pixels)), ceil(log2(VPL capacity))) and return it.  Later
+ * gathers with tile_vpl 0 in that bucket use it. */
+int vplg_autotune(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                  float* const radiance[3], const vplg_gather_params* p, void* stream, int32_t* best_tile_vpl);
+/* The tile_vpl a gather of this shape uses with tile_vpl 0 (8 if untuned). */
+int vplg_autotune_lookup(vplg_context* ctx, int32_t width, int32_t height, int32_t n_vpls, int32_t* tile_vpl);
+/* Save / merge the autotuned table as text ("vplg-autotune 1", then lines
+ * "log2_pixels log2_vpls tile_vpl").  load: ENOTFOUND if the file is absent. */
+int vplg_autotune_save(vplg_context* ctx, const char* path);
+int vplg_autotune_load(vplg_context* ctx, const char* path);
 
 #ifdef __cplusplus
 }

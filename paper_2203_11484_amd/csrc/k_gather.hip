@@ -23,6 +23,7 @@ constexpr int kGatherMaxWaves = 16;     // waves per gather workgroup (VPL slice
 constexpr int kGatherMaxThreads = 64 * kGatherMaxWaves;
 constexpr int kChunk = 16;              // VPLs per first-level partial sum of a wave
 constexpr int kXcds = 8;                // MI355X: 8 accelerator complex dies, one L2 each
+constexpr int kBatchWaves = kBatchBlockWaves;  // waves per persistent workgroup
 constexpr float kInvPi = 0.318309886183790671538f;
 
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -36,6 +37,8 @@ __device__ __forceinline__ float safe_inv(float d)
 
 struct Counters {
     unsigned long long rays = 0, nodes = 0, tris = 0;
+    // wave-level: packets traced, packet node steps, active lanes at packet start, packet triangle steps
+    unsigned long long packets = 0, psteps = 0, plane = 0, ptris = 0;
 };
 
 // Moller-Trumbore against leaf-ordered triangle i; returns the hit parameter
@@ -117,6 +120,7 @@ __device__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz,
         int c0 = __float_as_int(n3f.x), c1 = __float_as_int(n3f.y);
         int k0 = __float_as_int(n3f.z), k1 = __float_as_int(n3f.w);
         if (COUNT && alive) cnt.nodes++;
+        if (COUNT && lane == 0) cnt.psteps++;
         float lo0, hi0, lo1, hi1;
         child_boxes(n0, n1, n2, r, tlo, thi, &lo0, &hi0, &lo1, &hi1);
         bool h0 = alive && lo0 <= hi0 && c0 >= 0;
@@ -128,6 +132,7 @@ __device__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz,
                     float t, u, v;
                     int id;
                     if (COUNT && h0 && alive) cnt.tris++;
+                    if (COUNT && lane == 0) cnt.ptris++;
                     bool hit = tri_hit32(tris, i, ox, oy, oz, dx, dy, dz, d2, tlo, thi, ex0, ex1, &t, &u, &v, &id);
                     if (h0 && hit) alive = false;
                 }
@@ -140,6 +145,7 @@ __device__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz,
                     float t, u, v;
                     int id;
                     if (COUNT && h1 && alive) cnt.tris++;
+                    if (COUNT && lane == 0) cnt.ptris++;
                     bool hit = tri_hit32(tris, i, ox, oy, oz, dx, dy, dz, d2, tlo, thi, ex0, ex1, &t, &u, &v, &id);
                     if (h1 && hit) alive = false;
                 }
@@ -192,20 +198,19 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return t;
 }
 
-// One workgroup per 8 x 8 pixel tile; its waves split the VPLs (wave w takes
-// k = w, w + nw, ...), each wave tracing its shadow rays as one packet.  Per
-// wave the terms are summed in chunks of kChunk VPLs, chunk sums are added in
-// order, and the waves' sums are added in wave order: deterministic.
-template <bool COUNT>
-__global__ __launch_bounds__(kGatherMaxThreads) void k_gather(GatherArgs a)
+// Gather of one 8 x 8 pixel tile by a group of `nw` waves (wave `wave` of
+// the group takes k = wave, wave + nw, ...), each wave tracing its shadow
+// rays as one packet.  Per wave the terms are summed in chunks of kChunk
+// VPLs, chunk sums are added in order, and the group's waves are added in
+// wave order through `red` (LDS, [nw][3][64]): the result of a pixel depends
+// only on (tile, nw), never on what else runs in the launch.  All waves of
+// the group must call this together; `sync` is a barrier over the group.
+template <bool COUNT, class Sync>
+__device__ void gather_tile(const GatherArgs& a, int tile, int wave, int nw, int lane, float (*red)[3][64],
+                            Counters& cnt, unsigned long long& pairs, Sync sync)
 {
-    __shared__ float s_red[kGatherMaxWaves][3][64];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
     const int W = a.gb.width, H = a.gb.height;
-    const int tiles_x = (W + 7) >> 3, tiles_y = (H + 7) >> 3;
-    const int tile = xcd_tile(blockIdx.x, tiles_x * tiles_y);
+    const int tiles_x = (W + 7) >> 3;
     const int px = (tile % tiles_x) * 8 + (lane & 7);
     const int py = (tile / tiles_x) * 8 + (lane >> 3);
     const bool valid = px < W && py < H;
@@ -222,8 +227,6 @@ __global__ __launch_bounds__(kGatherMaxThreads) void k_gather(GatherArgs a)
     const float C = a.g_clamp;
     const float tlo = a.t_eps, thi = 1.0f - a.t_eps;
     const float4* __restrict__ vp = a.vpls.pack;
-    Counters cnt;
-    unsigned long long pairs = 0;
     float ar = 0.f, ag = 0.f, ab = 0.f;
     if (ballot(active) != 0) {
         for (int base = wave; base < M; base += nw * kChunk) {
@@ -239,6 +242,13 @@ __global__ __launch_bounds__(kGatherMaxThreads) void k_gather(GatherArgs a)
                 bool act = active && cp > 0.f && ck > 0.f;
                 if (ballot(act) == 0) continue;
                 if (COUNT && act) cnt.rays++;
+                if (COUNT) {
+                    const int n_act = __builtin_popcountll(ballot(act));
+                    if (lane == 0) {
+                        cnt.packets++;
+                        cnt.plane += n_act;
+                    }
+                }
                 float r2 = dx * dx + dy * dy + dz * dz;
                 float g = fminf(C, cp * ck * rcpf(r2 * r2));
                 bool vis = packet_visible<COUNT>(a.scene, x, y, z, dx, dy, dz, act, tlo, thi, tp, __float_as_int(v0.w),
@@ -255,31 +265,103 @@ __global__ __launch_bounds__(kGatherMaxThreads) void k_gather(GatherArgs a)
             ab += pb;
         }
     }
-    s_red[wave][0][lane] = ar;
-    s_red[wave][1][lane] = ag;
-    s_red[wave][2][lane] = ab;
-    __syncthreads();
+    red[wave][0][lane] = ar;
+    red[wave][1][lane] = ag;
+    red[wave][2][lane] = ab;
+    sync();
     if (wave == 0 && valid) {
         float sr = 0.f, sg = 0.f, sb = 0.f;
         for (int w = 0; w < nw; ++w) {
-            sr += s_red[w][0][lane];
-            sg += s_red[w][1][lane];
-            sb += s_red[w][2][lane];
+            sr += red[w][0][lane];
+            sg += red[w][1][lane];
+            sb += red[w][2][lane];
         }
         const float s = kInvPi;
         a.out[0][p] = active ? a.gb.alb[0][p] * s * sr : 0.f;
         a.out[1][p] = active ? a.gb.alb[1][p] * s * sg : 0.f;
         a.out[2][p] = active ? a.gb.alb[2][p] * s * sb : 0.f;
     }
-    if (COUNT) {
-        unsigned long long v[4] = {pairs, cnt.rays, cnt.nodes, cnt.tris};
-        for (int c = 0; c < 4; ++c) {
-            unsigned long long sum = v[c];
-            for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
-            if (lane == 0) atomicAdd(&a.counters[c], sum);
+    sync();
+}
+
+template <bool COUNT>
+__device__ __forceinline__ void flush_counters(unsigned long long* out, const Counters& cnt, unsigned long long pairs,
+                                               int lane)
+{
+    if (!COUNT) return;
+    unsigned long long v[8] = {pairs, cnt.rays, cnt.nodes, cnt.tris, cnt.packets, cnt.psteps, cnt.plane, cnt.ptris};
+    for (int c = 0; c < 8; ++c) {
+        unsigned long long sum = v[c];
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+        if (lane == 0) atomicAdd(&out[c], sum);
+    }
+}
+
+struct BlockSync {
+    __device__ void operator()() const { __syncthreads(); }
+};
+
+// One workgroup per 8 x 8 pixel tile (all its waves on that tile).
+template <bool COUNT>
+__global__ __launch_bounds__(kGatherMaxThreads) void k_gather(GatherArgs a)
+{
+    __shared__ float s_red[kGatherMaxWaves][3][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const int tiles = ((a.gb.width + 7) >> 3) * ((a.gb.height + 7) >> 3);
+    Counters cnt;
+    unsigned long long pairs = 0;
+    gather_tile<COUNT>(a, xcd_tile(blockIdx.x, tiles), wave, nw, lane, s_red, cnt, pairs, BlockSync());
+    flush_counters<COUNT>(a.counters, cnt, pairs, lane);
+}
+
+// Persistent gather over many views.  Each workgroup of kBatchWaves waves
+// claims work items from a device counter until none is left (every
+// workgroup reaches the exit).  Item i of view v covers tiles
+// [j * g, (j + 1) * g) with g = kBatchWaves / w_v tile groups of w_v waves.
+__global__ __launch_bounds__(64 * kBatchWaves) void k_gather_batch(const BatchTable* __restrict__ tab,
+                                                                    const GatherArgs* __restrict__ views,
+                                                                    unsigned int* __restrict__ counter)
+{
+    __shared__ float s_red[kBatchWaves][3][64];
+    __shared__ int s_item;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n_views = tab->n_views;
+    const int total = tab->prefix[n_views];
+    Counters cnt;
+    unsigned long long pairs = 0;
+    while (true) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        int lo = 0, hi = n_views;  // view: last v with prefix[v] <= item
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (tab->prefix[mid] <= item) lo = mid; else hi = mid;
+        }
+        const GatherArgs& a = views[lo];
+        const int w = tab->waves[lo];
+        const int groups = kBatchWaves / w;
+        const int group = wave / w;
+        const int tiles = ((a.gb.width + 7) >> 3) * ((a.gb.height + 7) >> 3);
+        const int tile = (item - tab->prefix[lo]) * groups + group;
+        // every wave takes part in both barriers, including groups past the last tile
+        const int t = tile < tiles ? tile : -1;
+        if (t >= 0) {
+            gather_tile<false>(a, t, wave % w, w, lane, s_red + group * w, cnt, pairs, BlockSync());
+        } else {
+            __syncthreads();
+            __syncthreads();
         }
     }
 }
+
+// Zero the work counter (a fill kernel: graph replays clear it reliably).
+__global__ void k_reset_counter(unsigned int* counter) { *counter = 0u; }
 
 // One lane per listed pixel; a wave walks the VPLs and records, per lane,
 // bit k % 32 of word k / 32 = V(x_p, y_k) for every pair (no geometry-term
@@ -434,6 +516,19 @@ hipError_t launch_gather(const GatherArgs& a, bool counted, hipStream_t s)
     else
         hipLaunchKernelGGL(k_gather<false>, grid, block, 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_gather_batch(const BatchTable* tab, const GatherArgs* views, unsigned int* counter, int blocks,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL(k_gather_batch, dim3(blocks), dim3(64 * kBatchWaves), 0, s, tab, views, counter);
+    return hipGetLastError();
+}
+
+hipError_t gather_batch_occupancy(int* blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gather_batch, 64 * kBatchWaves, 0);
 }
 
 hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s)

@@ -78,12 +78,30 @@ struct VplSetObj {
 
 }  // namespace
 
+// Persistent batched gather: device work table and view descriptors, their
+// pinned staging, and the HIP graph of (counter reset + persistent kernel).
+struct BatchEngine {
+    BatchTable* d_tab = nullptr;
+    GatherArgs* d_views = nullptr;
+    unsigned int* d_counter = nullptr;
+    BatchTable* h_tab = nullptr;
+    GatherArgs* h_views = nullptr;
+    hipEvent_t staged = nullptr;  // last use of the pinned staging
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int blocks = 0;
+    bool ready = false;
+};
+
 struct vplg_context {
     int device = 0;
     uint64_t budget = 0, used = 0;
     uint64_t next_id = 1;
     std::map<uint64_t, SceneObj*> scenes;
     std::map<uint64_t, VplSetObj*> sets;
+    BatchEngine batch;
+    std::map<uint32_t, int> tuned;  // view-shape bucket -> waves per 8 x 8 tile
 };
 
 namespace {
@@ -270,6 +288,16 @@ int vplg_context_destroy(vplg_context* ctx)
         free_all(ctx, kv.second->allocs);
         delete kv.second;
     }
+    BatchEngine& be = ctx->batch;
+    if (be.exec) (void)hipGraphExecDestroy(be.exec);
+    if (be.graph) (void)hipGraphDestroy(be.graph);
+    if (be.capture) (void)hipStreamDestroy(be.capture);
+    if (be.staged) (void)hipEventDestroy(be.staged);
+    if (be.d_tab) (void)hipFree(be.d_tab);
+    if (be.d_views) (void)hipFree(be.d_views);
+    if (be.d_counter) (void)hipFree(be.d_counter);
+    if (be.h_tab) (void)hipHostFree(be.h_tab);
+    if (be.h_views) (void)hipHostFree(be.h_views);
     delete ctx;
     return VPLG_OK;
 }
@@ -725,6 +753,25 @@ int vplg_vplset_release(vplg_context* ctx, uint64_t vplset_id)
     return VPLG_OK;
 }
 
+static uint32_t ceil_log2(long long x)
+{
+    uint32_t k = 0;
+    while ((1ll << k) < x) ++k;
+    return k;
+}
+
+// View-shape bucket of the autotuner: ceil(log2(pixels)), ceil(log2(VPLs)).
+static uint32_t shape_bucket(int width, int height, int n_vpls)
+{
+    return (ceil_log2((long long)width * height) << 8) | ceil_log2(n_vpls > 0 ? n_vpls : 1);
+}
+
+static int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls)
+{
+    auto it = ctx->tuned.find(shape_bucket(width, height, n_vpls));
+    return it == ctx->tuned.end() ? 8 : it->second;
+}
+
 static int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                          float* const radiance[3], const vplg_gather_params* p, GatherArgs* a)
 {
@@ -747,8 +794,8 @@ static int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_i
     a->g_clamp = p->g_clamp;
     a->t_eps = p->t_eps;
     a->counters = nullptr;
-    // tile_vpl: waves (VPL slices) per 8 x 8 tile; 0 = 8
-    int w = p->tile_vpl == 0 ? 8 : p->tile_vpl;
+    // tile_vpl: waves (VPL slices) per 8 x 8 tile; 0 = the autotuned choice for this view shape, else 8
+    int w = p->tile_vpl == 0 ? tuned_waves(ctx, gb->width, gb->height, v->dev.capacity) : p->tile_vpl;
     if (w < 1 || w > 16 || (w & (w - 1)))
         return fail(VPLG_EINVAL, "tile_vpl must be 0 or a power of two in [1, 16] (got %d)", p->tile_vpl);
     if (p->tile_px != 0 && p->tile_px != 64) return fail(VPLG_EINVAL, "tile_px must be 0 or 64 (8 x 8 pixels)");
@@ -802,6 +849,171 @@ int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t v
     a.bits = vis_bits;
     a.t_eps = p->t_eps;
     HIPCHK(launch_vis_dump(a, (hipStream_t)stream));
+    return VPLG_OK;
+}
+
+static int batch_init(vplg_context* ctx)
+{
+    BatchEngine& be = ctx->batch;
+    if (be.ready) return VPLG_OK;
+    HIPCHK(hipMalloc(&be.d_tab, sizeof(BatchTable)));
+    HIPCHK(hipMalloc(&be.d_views, sizeof(GatherArgs) * kBatchMaxViews));
+    HIPCHK(hipMalloc(&be.d_counter, sizeof(unsigned int)));
+    HIPCHK(hipHostMalloc(&be.h_tab, sizeof(BatchTable), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&be.h_views, sizeof(GatherArgs) * kBatchMaxViews, hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&be.staged, hipEventDisableTiming));
+    HIPCHK(hipStreamCreateWithFlags(&be.capture, hipStreamNonBlocking));
+    int cus = 0, per_cu = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    HIPCHK(gather_batch_occupancy(&per_cu));
+    be.blocks = cus * (per_cu > 0 ? per_cu : 1);
+    // the graph holds only fixed device pointers: the table's contents change between replays
+    HIPCHK(hipStreamBeginCapture(be.capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_gather_batch(be.d_tab, be.d_views, be.d_counter, be.blocks, be.capture);
+    hipError_t e2 = hipStreamEndCapture(be.capture, &be.graph);
+    if (e != hipSuccess) return fail(VPLG_EHIP, "batch capture: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(VPLG_EHIP, "batch capture end: %s", hipGetErrorString(e2));
+    HIPCHK(hipGraphInstantiate(&be.exec, be.graph, nullptr, nullptr, 0));
+    be.ready = true;
+    return VPLG_OK;
+}
+
+int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views, void* stream)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (n_views < 0 || n_views > kBatchMaxViews || (n_views > 0 && !views))
+        return fail(VPLG_EINVAL, "n_views must be in [0, %d]", kBatchMaxViews);
+    if (n_views == 0) return VPLG_OK;
+    // resolve and check every view before touching the staging buffers
+    std::vector<GatherArgs> args(n_views);
+    std::vector<int> waves(n_views), items(n_views);
+    std::vector<double> cost(n_views);
+    for (int v = 0; v < n_views; ++v) {
+        const vplg_view& vw = views[v];
+        if ((rc = gather_common(ctx, vw.scene_id, vw.vplset_id, &vw.gb, vw.radiance, &vw.params, &args[v])))
+            return fail(rc, "view %d: %s", v, g_err.c_str());
+        if (args[v].waves_per_tile > kBatchBlockWaves)
+            return fail(VPLG_EINVAL, "view %d: tile_vpl %d exceeds %d in a batch", v, args[v].waves_per_tile,
+                        kBatchBlockWaves);
+        waves[v] = args[v].waves_per_tile;
+        const int tiles = ((vw.gb.width + 7) / 8) * ((vw.gb.height + 7) / 8);
+        const int groups = kBatchBlockWaves / waves[v];
+        items[v] = (tiles + groups - 1) / groups;
+        cost[v] = (double)vw.gb.width * vw.gb.height * (double)args[v].vpls.capacity;
+    }
+    if ((rc = batch_init(ctx))) return rc;
+    BatchEngine& be = ctx->batch;
+    // most expensive views first (their tiles are claimed first), ties by index
+    std::vector<int> order(n_views);
+    for (int v = 0; v < n_views; ++v) order[v] = v;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    HIPCHK(hipEventSynchronize(be.staged));  // the previous call's copies have read the staging
+    long long total = 0;
+    for (int i = 0; i < n_views; ++i) {
+        int v = order[i];
+        be.h_tab->prefix[i] = (int)total;
+        be.h_tab->waves[i] = waves[v];
+        be.h_views[i] = args[v];
+        total += items[v];
+    }
+    if (total > 0x7fffffff) return fail(VPLG_EINVAL, "batch too large");
+    be.h_tab->prefix[n_views] = (int)total;
+    be.h_tab->n_views = n_views;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(be.d_tab, be.h_tab, sizeof(BatchTable), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(be.d_views, be.h_views, sizeof(GatherArgs) * n_views, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(be.staged, s));
+    HIPCHK(hipGraphLaunch(be.exec, s));
+    return VPLG_OK;
+}
+
+int vplg_autotune(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                  float* const radiance[3], const vplg_gather_params* p, void* stream, int32_t* best_tile_vpl)
+{
+    if (!p || !best_tile_vpl) return fail(VPLG_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best = 8;
+    int n_vpls = 0;
+    for (int w = 1; w <= kBatchBlockWaves; w <<= 1) {
+        vplg_gather_params q = *p;
+        q.tile_vpl = w;
+        GatherArgs a;
+        int rc = gather_common(ctx, scene_id, vplset_id, gb, radiance, &q, &a);
+        if (rc) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc;
+        }
+        n_vpls = a.vpls.capacity;
+        float ms = 0.f;
+        hipError_t e = launch_gather(a, false, s);  // warm
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch_gather(a, false, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return fail(VPLG_EHIP, "autotune: %s", hipGetErrorString(e));
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = w;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->tuned[shape_bucket(gb->width, gb->height, n_vpls)] = best;
+    *best_tile_vpl = best;
+    return VPLG_OK;
+}
+
+int vplg_autotune_lookup(vplg_context* ctx, int32_t width, int32_t height, int32_t n_vpls, int32_t* tile_vpl)
+{
+    if (!ctx || !tile_vpl) return fail(VPLG_EINVAL, "null argument");
+    *tile_vpl = tuned_waves(ctx, width, height, n_vpls);
+    return VPLG_OK;
+}
+
+int vplg_autotune_save(vplg_context* ctx, const char* path)
+{
+    if (!ctx || !path) return fail(VPLG_EINVAL, "null argument");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(VPLG_EINVAL, "cannot write %s", path);
+    std::fprintf(f, "vplg-autotune 1\n");
+    for (auto& kv : ctx->tuned) std::fprintf(f, "%u %u %d\n", kv.first >> 8, kv.first & 0xff, kv.second);
+    std::fclose(f);
+    return VPLG_OK;
+}
+
+int vplg_autotune_load(vplg_context* ctx, const char* path)
+{
+    if (!ctx || !path) return fail(VPLG_EINVAL, "null argument");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(VPLG_ENOTFOUND, "cannot read %s", path);
+    int version = 0;
+    if (std::fscanf(f, "vplg-autotune %d", &version) != 1 || version != 1) {
+        std::fclose(f);
+        return fail(VPLG_EINVAL, "%s is not an autotune cache", path);
+    }
+    unsigned px, nv;
+    int w;
+    std::map<uint32_t, int> t;
+    while (std::fscanf(f, "%u %u %d", &px, &nv, &w) == 3) {
+        if (px > 63 || nv > 255 || w < 1 || w > kBatchBlockWaves || (w & (w - 1))) {
+            std::fclose(f);
+            return fail(VPLG_EINVAL, "bad autotune entry in %s", path);
+        }
+        t[(px << 8) | nv] = w;
+    }
+    std::fclose(f);
+    for (auto& kv : t) ctx->tuned[kv.first] = kv.second;
     return VPLG_OK;
 }
 

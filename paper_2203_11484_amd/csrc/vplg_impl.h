@@ -80,6 +80,18 @@ struct GatherArgs {
     unsigned long long* counters;  // instrumented variant only
 };
 
+// Work table of a batched gather: views sorted by the caller, prefix[v] =
+// first work item of view v (prefix[n_views] = total), waves[v] = waves per
+// tile of view v (1, 2, 4 or 8).
+constexpr int kBatchBlockWaves = 8;
+constexpr int kBatchMaxViews = 4096;
+struct BatchTable {
+    int n_views;
+    int pad;
+    int prefix[kBatchMaxViews + 1];
+    int waves[kBatchMaxViews];
+};
+
 struct VisDumpArgs {
     DevScene scene;
     DevVpls vpls;
@@ -157,6 +169,9 @@ struct GenBuffers {
 // ---------------------------------------------------------------------------
 hipError_t launch_gather(const GatherArgs& a, bool counted, hipStream_t s);
 hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s);
+hipError_t launch_gather_batch(const BatchTable* tab, const GatherArgs* views, unsigned int* counter, int blocks,
+                               hipStream_t s);
+hipError_t gather_batch_occupancy(int* blocks_per_cu);
 hipError_t launch_gbuffer(const GBufferArgs& a, hipStream_t s);
 hipError_t launch_pack_vpls(const DevVpls& v, hipStream_t s);
 

@@ -66,6 +66,11 @@ class GatherParams(C.Structure):
     _fields_ = [("g_clamp", C.c_float), ("t_eps", C.c_float), ("tile_px", C.c_int32), ("tile_vpl", C.c_int32)]
 
 
+class View(C.Structure):
+    _fields_ = [("scene_id", C.c_uint64), ("vplset_id", C.c_uint64), ("gb", GBufferStruct),
+                ("radiance", C.c_void_p * 3), ("params", GatherParams)]
+
+
 _p = C.c_void_p
 _u64 = C.c_uint64
 _SIGS = {
@@ -91,6 +96,12 @@ _SIGS = {
                                       C.POINTER(GatherParams), _p, _p]),
     "vplg_gather_visibility_dump": (C.c_int, [_p, _u64, _u64, C.POINTER(GBufferStruct), _p, C.c_int32, _p,
                                               C.POINTER(GatherParams), _p]),
+    "vplg_gather_batch": (C.c_int, [_p, C.POINTER(View), C.c_int32, _p]),
+    "vplg_autotune": (C.c_int, [_p, _u64, _u64, C.POINTER(GBufferStruct), C.POINTER(_p), C.POINTER(GatherParams), _p,
+                                C.POINTER(C.c_int32)]),
+    "vplg_autotune_lookup": (C.c_int, [_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
+    "vplg_autotune_save": (C.c_int, [_p, C.c_char_p]),
+    "vplg_autotune_load": (C.c_int, [_p, C.c_char_p]),
 }
 
 
@@ -346,7 +357,7 @@ def gather(ctx, scene_id, vplset_id, gb, radiance, params=None, stream=None):
 
 
 def gather_counted(ctx, scene_id, vplset_id, gb, radiance, counters, params=None, stream=None):
-    """counters: torch uint64/int64 tensor of 4 on the device (pairs, rays, nodes, triangle tests)."""
+    """counters: torch int64 tensor of 8 on the device (see vplg_gather_counted in include/vplg.h)."""
     gp = params if isinstance(params, GatherParams) else make_gather_params(params)
     _check(lib().vplg_gather_counted(ctx, scene_id, vplset_id, C.byref(gb.struct), radiance_planes(radiance),
                                      C.byref(gp), C.c_void_p(counters.data_ptr()), _stream(stream)))
@@ -358,3 +369,47 @@ def gather_visibility_dump(ctx, scene_id, vplset_id, gb, pixels, vis_bits, param
     _check(lib().vplg_gather_visibility_dump(ctx, scene_id, vplset_id, C.byref(gb.struct),
                                              C.c_void_p(pixels.data_ptr()), int(pixels.numel()),
                                              C.c_void_p(vis_bits.data_ptr()), C.byref(gp), _stream(stream)))
+
+
+def make_views(views):
+    """views: list of dicts with scene, vplset, gb (GBuffer), radiance ((3, H, W) tensor), params (dict or
+    GatherParams).  Returns the ctypes array (keep it alive while the call runs)."""
+    arr = (View * len(views))()
+    for i, v in enumerate(views):
+        arr[i].scene_id = v["scene"]
+        arr[i].vplset_id = v["vplset"]
+        arr[i].gb = v["gb"].struct
+        rp = radiance_planes(v["radiance"])
+        for c in range(3):
+            arr[i].radiance[c] = rp[c]
+        p = v.get("params")
+        arr[i].params = p if isinstance(p, GatherParams) else make_gather_params(p)
+    return arr
+
+
+def gather_batch(ctx, views, stream=None):
+    arr = make_views(views)
+    _check(lib().vplg_gather_batch(ctx, arr, len(views), _stream(stream)))
+    return arr
+
+
+def autotune(ctx, scene_id, vplset_id, gb, radiance, params=None, stream=None):
+    gp = params if isinstance(params, GatherParams) else make_gather_params(params)
+    best = C.c_int32()
+    _check(lib().vplg_autotune(ctx, scene_id, vplset_id, C.byref(gb.struct), radiance_planes(radiance), C.byref(gp),
+                               _stream(stream), C.byref(best)))
+    return best.value
+
+
+def autotune_lookup(ctx, width, height, n_vpls):
+    w = C.c_int32()
+    _check(lib().vplg_autotune_lookup(ctx, int(width), int(height), int(n_vpls), C.byref(w)))
+    return w.value
+
+
+def autotune_save(ctx, path):
+    _check(lib().vplg_autotune_save(ctx, os.fsencode(path)))
+
+
+def autotune_load(ctx, path):
+    _check(lib().vplg_autotune_load(ctx, os.fsencode(path)))

@@ -1,0 +1,133 @@
+"""Batched gather (one persistent, graph-replayed launch over many views) and the tile autotuner."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as orc  # noqa: E402
+from paper_2203_11484_amd import scenes  # noqa: E402
+from tests import helpers as H  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vplg():
+    from paper_2203_11484_amd import vplg as v
+    v.lib()
+    return v
+
+
+@pytest.fixture(scope="module")
+def ctx(vplg):
+    c = vplg.context_create(0)
+    yield c
+    vplg.context_destroy(c)
+
+
+def _views(vplg, ctx):
+    """Six views over two scenes: ragged sizes, different VPL budgets and tile shapes."""
+    sc_a = scenes.make_scene("cornell")
+    sc_b = scenes.procedural_room(11, 6, 6, 2, 2, k_near=192, n_far=320, d_near=7.0)
+    ids = {}
+    for key, sc in (("a", sc_a), ("b", sc_b)):
+        ids[key] = (sc, vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"]))
+    specs = [("a", 40, 36, 1), ("b", 64, 64, 8), ("a", 100, 75, 4), ("b", 72, 40, 2), ("b", 33, 17, 8),
+             ("a", 128, 96, 0)]
+    views = []
+    for key, w, h, tv in specs:
+        sc, sid = ids[key]
+        cam = dict(sc["camera"])
+        cam["width"], cam["height"] = w, h
+        gb = vplg.GBuffer(w, h)
+        vplg.gbuffer_render(ctx, sid, cam, gb)
+        vid = vplg.vpls_generate(ctx, sid, cam, sc["params"])
+        rad = torch.full((3, h, w), -1.0, dtype=torch.float32, device="cuda")
+        gp = vplg.make_gather_params(sc["params"])
+        gp.tile_vpl = tv
+        views.append(dict(scene=sid, vplset=vid, gb=gb, radiance=rad, params=gp, sc=sc, cam=cam))
+    return views
+
+
+def test_batch_equals_per_view_and_replays(vplg, ctx):
+    views = _views(vplg, ctx)
+    refs = []
+    for v in views:
+        r = torch.zeros_like(v["radiance"])
+        vplg.gather(ctx, v["scene"], v["vplset"], v["gb"], r, v["params"])
+        refs.append(r)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for v in views:
+            v["radiance"].fill_(-1.0)
+        vplg.gather_batch(ctx, views)
+        torch.cuda.synchronize()
+        for i, v in enumerate(views):
+            assert torch.equal(v["radiance"], refs[i]), f"replay {rep}: view {i} differs from its single gather"
+        # eager work between replays
+        _ = (torch.ones(1 << 20, device="cuda") * 2).sum().item()
+    # a different subset and order in the next replay
+    sub = [views[4], views[0], views[2]]
+    for v in sub:
+        v["radiance"].fill_(-1.0)
+    vplg.gather_batch(ctx, sub)
+    torch.cuda.synchronize()
+    for v in sub:
+        i = views.index(v)
+        assert torch.equal(v["radiance"], refs[i])
+
+
+def test_batch_view_matches_oracle(vplg, ctx):
+    """One batched view against the oracle on its own inputs (the oracle's G-buffer and VPLs)."""
+    sc = scenes.make_scene("cornell", width=48, height=40)
+    S = orc.Scene.from_dict(sc)
+    gbo = S.gbuffer(sc["camera"])
+    g = S.generate(sc["camera"], sc["light"], sc["params"])
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
+    gb = vplg.GBuffer.from_arrays(gbo["pos"], gbo["nrm"], gbo["alb"], gbo["tri"], 48, 40)
+    vid = vplg.vpls_upload(ctx, g["pos"], g["nrm"], g["I"], g["tri"])
+    other = _views(vplg, ctx)[:2]
+    rad = torch.zeros((3, 40, 48), dtype=torch.float32, device="cuda")
+    vplg.gather_batch(ctx, other + [dict(scene=sid, vplset=vid, gb=gb, radiance=rad, params=sc["params"])])
+    torch.cuda.synchronize()
+    L_gpu = rad.cpu().numpy().reshape(3, -1).T
+    f = gb.to_numpy()
+    L_ref = S.gather(f["pos"], f["nrm"], f["alb"], f["tri"], g["pos"].astype(np.float32), g["nrm"].astype(np.float32),
+                     g["I"].astype(np.float32), g["tri"])
+    ok = H.radiance_close(L_gpu, L_ref)
+    assert ok.mean() > 0.995, (~ok).sum()
+
+
+def test_batch_rejects_bad_views(vplg, ctx):
+    views = _views(vplg, ctx)[:2]
+    bad = dict(views[1])
+    bad["vplset"] = 123456789
+    with pytest.raises(vplg.VplgError) as e:
+        vplg.gather_batch(ctx, [views[0], bad])
+    assert e.value.code == vplg.ENOTFOUND
+    gp = vplg.make_gather_params()
+    gp.tile_vpl = 16
+    big = dict(views[0])
+    big["params"] = gp
+    with pytest.raises(vplg.VplgError) as e:
+        vplg.gather_batch(ctx, [big])
+    assert e.value.code == vplg.EINVAL
+
+
+def test_autotune_roundtrip(vplg, ctx, tmp_path):
+    v = _views(vplg, ctx)[1]
+    best = vplg.autotune(ctx, v["scene"], v["vplset"], v["gb"], v["radiance"], v["params"])
+    assert best in (1, 2, 4, 8)
+    n = vplg.vplset_count(ctx, v["vplset"])
+    assert vplg.autotune_lookup(ctx, v["gb"].width, v["gb"].height, n) == best
+    path = os.path.join(tmp_path, "tune.txt")
+    vplg.autotune_save(ctx, path)
+    c2 = vplg.context_create(0)
+    try:
+        assert vplg.autotune_lookup(c2, v["gb"].width, v["gb"].height, n) == 8
+        vplg.autotune_load(c2, path)
+        assert vplg.autotune_lookup(c2, v["gb"].width, v["gb"].height, n) == best
+    finally:
+        vplg.context_destroy(c2)
