@@ -72,6 +72,177 @@ def cpu_baseline(sc, target_s, seed=0):
                        f"{g['n']} VPLs ({pairs} pairs, FP64, {dt:.1f} s)")
 
 
+def bench_batch(args):
+    """64 views over 8 seeded rooms of 5k-200k triangles, resolutions from {256^2, 512^2, 1024^2, 1920x1080},
+    VPL budgets log-uniform in [1024, 16384]: one persistent batched launch against 64 plain launches."""
+    import numpy as np
+    import torch
+
+    from paper_2203_11484_amd import scenes, vplg
+
+    scs = scenes.batch_scenes()
+    vs = scenes.batch_views(scs)
+    torch.cuda.init()
+    ctx = vplg.context_create(0)
+    stream = torch.cuda.current_stream()
+    sids = [vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"], stream) for sc in scs]
+    views = []
+    pairs = 0
+    for v in vs:
+        cam = v["camera"]
+        gb = vplg.GBuffer(cam["width"], cam["height"])
+        vplg.gbuffer_render(ctx, sids[v["scene"]], cam, gb, stream)
+        vid = vplg.vpls_generate(ctx, sids[v["scene"]], cam, v["params"], stream)
+        rad = torch.zeros((3, cam["height"], cam["width"]), dtype=torch.float32, device="cuda")
+        views.append(dict(scene=sids[v["scene"]], vplset=vid, gb=gb, radiance=rad, params=dict(v["params"])))
+    torch.cuda.synchronize()
+    for v in views:
+        pairs += v["gb"].width * v["gb"].height * vplg.vplset_count(ctx, v["vplset"])
+    print(f"bench: batch of {len(views)} views, {pairs:.3e} pairs", file=sys.stderr, flush=True)
+    tuned = {}
+    if args.autotune:
+        for v in views:
+            key = (v["gb"].width * v["gb"].height, vplg.vplset_count(ctx, v["vplset"]).bit_length())
+            if key not in tuned:
+                tuned[key] = vplg.autotune(ctx, v["scene"], v["vplset"], v["gb"], v["radiance"], v["params"], stream)
+        print(f"bench: autotuned {tuned}", file=sys.stderr, flush=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    vplg.gather_batch(ctx, views, stream)  # warm-up: captures the graph
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(args.steps):
+        vplg.gather_batch(ctx, views, stream)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ref = [v["radiance"].clone() for v in views]
+    ev[2].record(stream)
+    for v in views:  # the plain one-frame-per-launch gather of the same views
+        vplg.gather(ctx, v["scene"], v["vplset"], v["gb"], v["radiance"], v["params"], stream)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, v["radiance"]) for a, v in zip(ref, views))
+    t_batch = ev[0].elapsed_time(ev[1]) / args.steps / 1e3
+    t_plain = ev[2].elapsed_time(ev[3]) / 1e3
+    out = {
+        "metric": "VPL-pixel shading pairs/sec incl. visibility (1 GPU), batched",
+        "value": pairs / t_batch, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64", "views": len(views), "scenes": len(scs),
+                   "triangles": [int(len(sc["tri"])) for sc in scs], "pairs": int(pairs)},
+        "plain_launches": {"value": pairs / t_plain, "unit": "pairs/s", "ms": t_plain * 1e3},
+        "batched_equals_plain": bool(same),
+        "autotuned": {f"{k[0]}px_{k[1]}": w for k, w in tuned.items()},
+    }
+    vplg.context_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+def serve_requests(n, seed=300):
+    """Seeded request stream over the 8 batch scenes: resolution from {256^2, 512^2, 1024^2, 1920x1080},
+    VPL budget log-uniform in [1024, 32768] (multiple of 64, split 1:1)."""
+    import numpy as np
+
+    from paper_2203_11484_amd import scenes
+
+    scs = scenes.batch_scenes()
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n):
+        si = int(rng.integers(len(scs)))
+        w, h = scenes.RESOLUTIONS[int(rng.integers(len(scenes.RESOLUTIONS)))]
+        m = max(64, int(round(math.exp(rng.uniform(math.log(1024), math.log(32768))) / 64.0)) * 64)
+        cam = scenes._view_camera(rng, scs[si], w, h)
+        reqs.append((si, cam, scenes.default_params(k_near=m // 2, n_far=m - m // 2, d_near=7.0)))
+    return scs, reqs
+
+
+def bench_serve(args):
+    """Poisson request stream at 0.7 x the plain path's capacity: the continuous-batching server against the
+    plain FIFO one-frame-per-launch loop on the same arrival trace; p50 / p99 latency and throughput."""
+    import numpy as np
+    import torch
+
+    from paper_2203_11484_amd import vplg
+
+    n_warm, n = 8, args.requests
+    scs, reqs = serve_requests(n_warm + n)
+    torch.cuda.init()
+    ctx = vplg.context_create(0)
+    stream = torch.cuda.current_stream()
+    sids = [vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"], stream) for sc in scs]
+    outs = [torch.zeros((3, c["height"], c["width"]), dtype=torch.float32, device="cuda") for _, c, _ in reqs]
+
+    def plain(i):
+        si, cam, prm = reqs[i]
+        gb = vplg.GBuffer(cam["width"], cam["height"])
+        vplg.gbuffer_render(ctx, sids[si], cam, gb, stream)
+        vid = vplg.vpls_generate(ctx, sids[si], cam, prm, stream)
+        vplg.gather(ctx, sids[si], vid, gb, outs[i], prm, stream)
+        torch.cuda.synchronize()
+        vplg.vplset_release(ctx, vid)
+
+    t = time.perf_counter()
+    for i in range(n_warm):
+        plain(i)
+    service = (time.perf_counter() - t) / n_warm
+    rate = 0.7 / service
+    rng = np.random.default_rng(301)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+    print(f"bench: serve {n} requests, mean plain service {service * 1e3:.1f} ms, rate {rate:.2f}/s",
+          file=sys.stderr, flush=True)
+    # plain FIFO loop on the arrival trace
+    lat_plain = []
+    t0 = time.perf_counter()
+    for j in range(n):
+        while time.perf_counter() - t0 < arrivals[j]:
+            time.sleep(0.0005)
+        plain(n_warm + j)
+        lat_plain.append(time.perf_counter() - t0 - arrivals[j])
+    span_plain = time.perf_counter() - t0
+    ref = [outs[n_warm + j].clone() for j in range(n)]
+    for j in range(n):
+        outs[n_warm + j].fill_(-1.0)
+    torch.cuda.synchronize()
+    # the server on the same trace
+    srv = vplg.server_start(ctx, 2 << 30, max_inflight=8, n_streams=4)
+    keep, tickets = [], []
+    t0 = time.perf_counter()
+    base_ns = time.monotonic_ns()
+    for j in range(n):
+        while time.perf_counter() - t0 < arrivals[j]:
+            time.sleep(0.0005)
+        si, cam, prm = reqs[n_warm + j]
+        r = vplg.make_request(sids[si], cam, prm, outs[n_warm + j])
+        keep.append(r)
+        tickets.append(vplg.server_submit(srv, r))
+    times = [vplg.server_wait(srv, tk, timeout_ms=600000) for tk in tickets]
+    st = vplg.server_query(srv)
+    vplg.server_stop(srv)
+    torch.cuda.synchronize()
+    lat_srv = [(tm["done_ns"] - tm["submit_ns"]) / 1e9 for tm in times]
+    span_srv = (max(tm["done_ns"] for tm in times) - min(tm["submit_ns"] for tm in times)) / 1e9
+    same = all(torch.equal(ref[j], outs[n_warm + j]) for j in range(n))
+    pairs = sum(c["width"] * c["height"] * (p["k_near"] + p["n_far"]) for _, c, p in reqs[n_warm:])
+    out = {
+        "metric": "VPL-pixel shading pairs/sec incl. visibility (1 GPU), served; p99 frame latency",
+        "value": pairs / span_srv, "unit": "pairs/s", "n_gpus": 1, "steps": n, "warmup": n_warm,
+        "ms_per_step": span_srv / n * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serve", "requests": n, "arrival_rate_per_s": rate, "budget_bytes": 2 << 30,
+                   "max_inflight": 8, "streams": 4},
+        "server": {"p50_ms": float(np.percentile(lat_srv, 50) * 1e3), "p99_ms": float(np.percentile(lat_srv, 99) * 1e3),
+                   "throughput_req_per_s": n / span_srv, "peak_running": st["peak_running"],
+                   "peak_bytes": st["peak_bytes"]},
+        "plain_fifo": {"p50_ms": float(np.percentile(lat_plain, 50) * 1e3),
+                       "p99_ms": float(np.percentile(lat_plain, 99) * 1e3), "throughput_req_per_s": n / span_plain,
+                       "pairs_per_s": pairs / span_plain},
+        "served_equals_alone": bool(same),
+    }
+    vplg.context_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +252,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile-vpl", type=int, default=0, help="waves (VPL slices) per 8x8 pixel tile, 0 = default")
+    ap.add_argument("--autotune", action="store_true", help="batch64: autotune tile_vpl per view-shape bucket")
+    ap.add_argument("--requests", type=int, default=64, help="serve: requests after 8 warm-ups")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -88,6 +261,11 @@ def main():
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch

@@ -278,6 +278,65 @@ int vplg_autotune_lookup(vplg_context* ctx, int32_t width, int32_t height, int32
 int vplg_autotune_save(vplg_context* ctx, const char* path);
 int vplg_autotune_load(vplg_context* ctx, const char* path);
 
+/* ------------------------------------------------------------------------ */
+/* Render server: continuous admission under an HBM budget                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct vplg_server vplg_server;
+
+/* hbm_budget_bytes: device memory the server may hold for per-request
+ * G-buffers and VPL sets (pooled; > 0).  max_inflight: requests admitted at
+ * once (1..256).  n_streams: HIP streams the admitted requests are spread
+ * over (1..16, default priority). */
+typedef struct {
+    uint64_t hbm_budget_bytes;
+    int32_t max_inflight, n_streams;
+} vplg_server_params;
+
+/* One render: the resident scene, the camera (its width x height is the
+ * image), generation and gather parameters, and the caller-owned device
+ * radiance planes (width * height float32 each) the result is written to. */
+typedef struct {
+    uint64_t scene_id;
+    vplg_camera camera;
+    vplg_gen_params gen;
+    vplg_gather_params gather;
+    float* radiance[3];
+} vplg_request;
+
+enum { VPLG_REQ_QUEUED = 0, VPLG_REQ_RUNNING = 1, VPLG_REQ_DONE = 2, VPLG_REQ_FAILED = 3, VPLG_REQ_CANCELLED = 4 };
+
+/* State of a request and its host steady-clock times (ns): submitted,
+ * admitted (its work enqueued), done (completion observed). */
+typedef struct {
+    int32_t state, error;
+    int64_t submit_ns, admit_ns, done_ns;
+} vplg_timing;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed, cancelled, queued, running, peak_running;
+    uint64_t pool_bytes, peak_bytes;
+} vplg_server_stats;
+
+/* Start the server thread.  While a server runs, the context's scenes must
+ * not be released; other calls on the context stay allowed. */
+int vplg_server_start(vplg_context* ctx, const vplg_server_params* p, vplg_server** out);
+/* Queue a request (thread-safe).  Returns at once with a ticket.  EBUDGET if
+ * the request alone exceeds the server budget; EINVAL / ENOTFOUND for bad
+ * arguments.  The first request on a (scene, patch_h) pair synchronises once
+ * to build the scene's patch index. */
+int vplg_server_submit(vplg_server* s, const vplg_request* r, uint64_t* ticket);
+/* Current state and times of a ticket (thread-safe, non-blocking). */
+int vplg_server_poll(vplg_server* s, uint64_t ticket, vplg_timing* t);
+/* Block until the ticket is done, failed or cancelled (timeout_ms < 0: no
+ * limit; ETIMEOUT otherwise).  VPLG_OK only if it is done. */
+int vplg_server_wait(vplg_server* s, uint64_t ticket, int64_t timeout_ms, vplg_timing* t);
+/* Cancel a queued request; EBUSY once it has been admitted. */
+int vplg_server_cancel(vplg_server* s, uint64_t ticket);
+int vplg_server_query(vplg_server* s, vplg_server_stats* out);
+/* Cancel queued requests, let admitted ones finish, free the pool, join. */
+int vplg_server_stop(vplg_server* s);
+
 #ifdef __cplusplus
 }
 #endif

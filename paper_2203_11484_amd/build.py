@@ -25,6 +25,7 @@ SOURCES = [
     ("k_generate.hip", ["-ffp-contract=off"]),
     ("bvh_build.cpp", []),
     ("runtime.cpp", ["-ffp-contract=off"]),
+    ("server.cpp", []),
 ]
 
 
@@ -48,7 +49,7 @@ def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(lambda s: _compile(s[0], s[1], verbose), SOURCES))
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", OUT + ".tmp", *objs]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", OUT + ".tmp", *objs, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -10,17 +10,14 @@
 #include <string>
 #include <vector>
 
-#include "vplg.h"
-#include "vplg_impl.h"
 
-namespace vplg {
-bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vector<float4>& out_tris, int* n_leaves,
-               int* max_depth, std::string& err);
-}
+#include "runtime_internal.h"
 
 using namespace vplg;
+using namespace vplg::rt;
 
-namespace {
+namespace vplg {
+namespace rt {
 
 thread_local std::string g_err;
 
@@ -35,79 +32,9 @@ int fail(int code, const char* fmt, ...)
     return code;
 }
 
-#define HIPCHK(expr)                                                                           \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) return fail(VPLG_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-struct Alloc {
-    void* p;
-    size_t bytes;
-};
-
-struct PatchIndex {
-    double h;
-    int32_t* level;
-    long long* off;
-    long long total;
-};
-
-struct SceneObj {
-    DevScene dev;
-    DevLight light;
-    std::vector<Alloc> allocs;
-    uint64_t bytes = 0;
-    vplg_scene_info info;
-    std::vector<PatchIndex> patches;
-};
-
-struct VplSetObj {
-    DevVpls dev;
-    std::vector<Alloc> allocs;
-    uint64_t bytes = 0;
-    bool generated = false;
-    GenBuffers gen;
-    int k_near = 0;
-    int n_far = 0;
-    int n_tris = 0;
-    uint64_t scene_id = 0;
-    double patch_h = 0.0;
-    hipEvent_t done = nullptr;
-};
-
-}  // namespace
-
-// Persistent batched gather: device work table and view descriptors, their
-// pinned staging, and the HIP graph of (counter reset + persistent kernel).
-struct BatchEngine {
-    BatchTable* d_tab = nullptr;
-    GatherArgs* d_views = nullptr;
-    unsigned int* d_counter = nullptr;
-    BatchTable* h_tab = nullptr;
-    GatherArgs* h_views = nullptr;
-    hipEvent_t staged = nullptr;  // last use of the pinned staging
-    hipStream_t capture = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int blocks = 0;
-    bool ready = false;
-};
-
-struct vplg_context {
-    int device = 0;
-    uint64_t budget = 0, used = 0;
-    uint64_t next_id = 1;
-    std::map<uint64_t, SceneObj*> scenes;
-    std::map<uint64_t, VplSetObj*> sets;
-    BatchEngine batch;
-    std::map<uint32_t, int> tuned;  // view-shape bucket -> waves per 8 x 8 tile
-};
-
-namespace {
-
 int dalloc(vplg_context* ctx, std::vector<Alloc>& list, uint64_t& acc, size_t bytes, void** out)
 {
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     if (bytes == 0) bytes = 16;
     bytes = (bytes + 255) & ~(size_t)255;
     if (ctx->budget && ctx->used + bytes > ctx->budget)
@@ -126,17 +53,9 @@ int dalloc(vplg_context* ctx, std::vector<Alloc>& list, uint64_t& acc, size_t by
     return VPLG_OK;
 }
 
-template <class T>
-int dalloc_n(vplg_context* ctx, std::vector<Alloc>& list, uint64_t& acc, size_t n, T** out)
-{
-    void* p = nullptr;
-    int rc = dalloc(ctx, list, acc, n * sizeof(T), &p);
-    *out = (T*)p;
-    return rc;
-}
-
 void free_all(vplg_context* ctx, std::vector<Alloc>& list)
 {
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     for (auto& a : list) {
         (void)hipFree(a.p);
         ctx->used -= a.bytes;
@@ -153,12 +72,14 @@ int set_device(vplg_context* ctx)
 
 SceneObj* find_scene(vplg_context* ctx, uint64_t id)
 {
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     auto it = ctx->scenes.find(id);
     return it == ctx->scenes.end() ? nullptr : it->second;
 }
 
 VplSetObj* find_set(vplg_context* ctx, uint64_t id)
 {
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     auto it = ctx->sets.find(id);
     return it == ctx->sets.end() ? nullptr : it->second;
 }
@@ -255,7 +176,8 @@ int set_count(VplSetObj* v, int32_t* n)
     return VPLG_OK;
 }
 
-}  // namespace
+}  // namespace rt
+}  // namespace vplg
 
 extern "C" {
 
@@ -402,6 +324,7 @@ int vplg_scene_upload(vplg_context* ctx, const float* tri_xyz, const float* tri_
         so->info.lo[k] = d.lo[k];
         so->info.hi[k] = d.hi[k];
     }
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     uint64_t id = ctx->next_id++;
     ctx->scenes[id] = so;
     *scene_id = id;
@@ -415,6 +338,7 @@ int vplg_scene_release(vplg_context* ctx, uint64_t scene_id)
     SceneObj* so = find_scene(ctx, scene_id);
     if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
     HIPCHK(hipDeviceSynchronize());
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     free_all(ctx, so->allocs);
     delete so;
     ctx->scenes.erase(scene_id);
@@ -431,17 +355,13 @@ int vplg_scene_describe(vplg_context* ctx, uint64_t scene_id, vplg_scene_info* o
     return VPLG_OK;
 }
 
-int vplg_gbuffer_render(vplg_context* ctx, uint64_t scene_id, const vplg_camera* cam, const vplg_gbuffer* gb,
-                        void* stream)
+}  // extern "C"
+
+namespace vplg {
+namespace rt {
+
+int render_gbuffer(SceneObj* so, const vplg_camera* cam, const vplg_gbuffer* gb, hipStream_t s)
 {
-    int rc = set_device(ctx);
-    if (rc) return rc;
-    SceneObj* so = find_scene(ctx, scene_id);
-    if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
-    if ((rc = check_camera(cam)) || (rc = check_gbuffer(gb))) return rc;
-    if (gb->width != cam->width || gb->height != cam->height)
-        return fail(VPLG_EINVAL, "gbuffer %dx%d does not match camera %dx%d", gb->width, gb->height, cam->width,
-                    cam->height);
     CamBasis k = cam_basis(cam);
     GBufferArgs a;
     a.scene = so->dev;
@@ -459,11 +379,11 @@ int vplg_gbuffer_render(vplg_context* ctx, uint64_t scene_id, const vplg_camera*
     a.tri = gb->tri;
     a.width = gb->width;
     a.height = gb->height;
-    HIPCHK(launch_gbuffer(a, (hipStream_t)stream));
+    HIPCHK(launch_gbuffer(a, s));
     return VPLG_OK;
 }
 
-static int check_gen_params(const vplg_gen_params* p)
+int check_gen_params(const vplg_gen_params* p)
 {
     if (!p) return fail(VPLG_EINVAL, "null parameters");
     if (p->k_near < 0 || p->n_far < 0 || (long long)p->k_near + p->n_far > (1 << 26))
@@ -476,6 +396,161 @@ static int check_gen_params(const vplg_gen_params* p)
     return VPLG_OK;
 }
 
+int patch_index(vplg_context* ctx, SceneObj* so, double h, hipStream_t s, PatchIndex** out)
+{
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    for (auto& x : so->patches)
+        if (x.h == h) {
+            *out = &x;
+            return VPLG_OK;
+        }
+    const int T = so->dev.n_tris;
+    PatchIndex x;
+    x.h = h;
+    long long* counts = nullptr;
+    std::vector<Alloc> tmp;
+    uint64_t tmp_bytes = 0;
+    long long* scan_tmp = nullptr;
+    int need = scan_tmp_needed(T);
+    int rc;
+    if ((rc = dalloc_n(ctx, so->allocs, so->bytes, (size_t)T, &x.level)) ||
+        (rc = dalloc_n(ctx, so->allocs, so->bytes, (size_t)T + 1, &x.off)) ||
+        (rc = dalloc_n(ctx, tmp, tmp_bytes, (size_t)T, &counts)) ||
+        (rc = dalloc_n(ctx, tmp, tmp_bytes, (size_t)need, &scan_tmp))) {
+        free_all(ctx, tmp);
+        return rc;
+    }
+    hipError_t e = launch_patch_levels(so->dev, h, x.level, counts, s);
+    if (e == hipSuccess) e = launch_scan_i64(counts, x.off, T, scan_tmp, need, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&x.total, x.off + T, sizeof(long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    free_all(ctx, tmp);
+    if (e != hipSuccess) return fail(VPLG_EHIP, "patch index: %s", hipGetErrorString(e));
+    if (x.total > (1ll << 30)) return fail(VPLG_EINVAL, "too many patches (%lld) for patch_h", x.total);
+    so->patches.push_back(x);
+    so->info.device_bytes = so->bytes;
+    *out = &so->patches.back();
+    return VPLG_OK;
+}
+
+namespace {
+
+// Allocation plan of a generated set: element counts of every array.
+struct GensetShape {
+    size_t cap1, np1, n2, strata;
+    int batch, scan_tmp_len;
+};
+
+GensetShape genset_shape(long long NP, int k_near, int n_far)
+{
+    GensetShape g;
+    const int cap = k_near + n_far;
+    g.cap1 = cap > 0 ? (size_t)cap : 1;
+    g.np1 = NP > 0 ? (size_t)NP : 1;
+    long long n2 = 2048;
+    while (n2 < NP) n2 <<= 1;
+    g.n2 = (size_t)n2;
+    g.strata = (size_t)std::max(1, k_near);
+    int batch = 4096;
+    while (batch < 4 * cap && batch < 65536) batch <<= 1;
+    g.batch = batch;
+    g.scan_tmp_len = scan_tmp_needed((int)std::max<long long>(NP, 1));
+    return g;
+}
+
+size_t round256(size_t b) { return ((b ? b : 16) + 255) & ~(size_t)255; }
+
+}  // namespace
+
+uint64_t genset_bytes(long long NP, int k_near, int n_far)
+{
+    GensetShape g = genset_shape(NP, k_near, n_far);
+    size_t c = g.cap1, n = g.np1, b = (size_t)g.batch;
+    size_t sizes[] = {c * 4, c * 4, c * 4, c * 4, c * 4, c * 4, c * 4, c * 4, c * 4, c * 4, 4, 3 * c * 16,
+                      n, g.n2 * 8, n * 4, n * 4, g.strata * 4, c * 4, c * 4, sizeof(GenState), n * 8, (n + 1) * 8,
+                      3 * c * 8, 3 * c * 8, b * 4, 9 * b * 8, 9 * b * 8, 3 * b * 4, 3 * b * 4,
+                      (size_t)g.scan_tmp_len * 8};
+    uint64_t total = 0;
+    for (size_t x : sizes) total += round256(x);
+    return total;
+}
+
+int alloc_genset(vplg_context* ctx, SceneObj* so, uint64_t scene_id, PatchIndex* pi, const vplg_gen_params* p,
+                 VplSetObj** out)
+{
+    const long long NP = pi->total;
+    GensetShape g = genset_shape(NP, p->k_near, p->n_far);
+    auto* v = new VplSetObj;
+    v->generated = true;
+    v->k_near = p->k_near;
+    v->n_far = p->n_far;
+    v->n_tris = so->dev.n_tris;
+    v->scene_id = scene_id;
+    v->patch_h = p->patch_h;
+    DevVpls& dv = v->dev;
+    GenBuffers& b = v->gen;
+    std::memset(&b, 0, sizeof b);
+    b.n_patches = (int)NP;
+    b.level = pi->level;
+    b.patch_off = pi->off;
+    b.batch = g.batch;
+    b.scan_tmp_len = g.scan_tmp_len;
+    const size_t c = g.cap1, n = g.np1, bt = (size_t)g.batch;
+    int rc;
+    auto A = [&](auto** ptr, size_t k) { return dalloc_n(ctx, v->allocs, v->bytes, k, ptr); };
+    if ((rc = A(&dv.px, c)) || (rc = A(&dv.py, c)) || (rc = A(&dv.pz, c)) || (rc = A(&dv.nx, c)) ||
+        (rc = A(&dv.ny, c)) || (rc = A(&dv.nz, c)) || (rc = A(&dv.ir, c)) || (rc = A(&dv.ig, c)) ||
+        (rc = A(&dv.ib, c)) || (rc = A(&dv.tri, c)) || (rc = A(&dv.count, 1)) || (rc = A(&dv.pack, 3 * c)) ||
+        (rc = A(&b.pflags, n)) || (rc = A(&b.sortbuf, g.n2)) || (rc = A(&b.sorted, n)) || (rc = A(&b.keys, n)) ||
+        (rc = A(&b.strata, g.strata)) || (rc = A(&b.vpl_path, c)) || (rc = A(&b.vpl_bounce, c)) ||
+        (rc = A(&b.state, 1)) || (rc = A(&b.q, n)) || (rc = A(&b.scan_out, n + 1)) ||
+        (rc = A(&b.stage_pos, 3 * c)) || (rc = A(&b.stage_flux, 3 * c)) || (rc = A(&b.w_count, bt)) ||
+        (rc = A(&b.w_pos, 9 * bt)) || (rc = A(&b.w_flux, 9 * bt)) || (rc = A(&b.w_tri, 3 * bt)) ||
+        (rc = A(&b.w_bounce, 3 * bt)) || (rc = A(&b.scan_tmp, (size_t)b.scan_tmp_len))) {
+        release_set(ctx, v);
+        return rc;
+    }
+    dv.capacity = p->k_near + p->n_far;
+    b.F = b.scan_out + 1;
+    hipError_t e = hipEventCreateWithFlags(&v->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        v->done = nullptr;
+        release_set(ctx, v);
+        return fail(VPLG_EHIP, "event: %s", hipGetErrorString(e));
+    }
+    *out = v;
+    return VPLG_OK;
+}
+
+int launch_genset(SceneObj* so, VplSetObj* v, const vplg_camera* cam, const vplg_gen_params* p, hipStream_t s)
+{
+    CamBasis cb = cam_basis(cam);
+    GenParams gp{p->k_near, p->n_far, p->max_bounces, p->max_paths, p->d_near, p->patch_h, p->t_eps};
+    HIPCHK(launch_generate(so->dev, so->light, cb, gp, v->dev, v->gen, s));
+    HIPCHK(launch_pack_vpls(v->dev, s));
+    HIPCHK(hipEventRecord(v->done, s));
+    return VPLG_OK;
+}
+
+}  // namespace rt
+}  // namespace vplg
+
+extern "C" {
+
+int vplg_gbuffer_render(vplg_context* ctx, uint64_t scene_id, const vplg_camera* cam, const vplg_gbuffer* gb,
+                        void* stream)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    SceneObj* so = find_scene(ctx, scene_id);
+    if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
+    if ((rc = check_camera(cam)) || (rc = check_gbuffer(gb))) return rc;
+    if (gb->width != cam->width || gb->height != cam->height)
+        return fail(VPLG_EINVAL, "gbuffer %dx%d does not match camera %dx%d", gb->width, gb->height, cam->width,
+                    cam->height);
+    return render_gbuffer(so, cam, gb, (hipStream_t)stream);
+}
+
 int vplg_vpls_generate(vplg_context* ctx, uint64_t scene_id, const vplg_camera* cam, const vplg_gen_params* p,
                        void* stream, uint64_t* vplset_id)
 {
@@ -486,88 +561,15 @@ int vplg_vpls_generate(vplg_context* ctx, uint64_t scene_id, const vplg_camera* 
     if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
     if ((rc = check_camera(cam)) || (rc = check_gen_params(p))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const int T = so->dev.n_tris;
-    // patch index of the scene for this h (computed once, then resident)
     PatchIndex* pi = nullptr;
-    for (auto& x : so->patches)
-        if (x.h == p->patch_h) pi = &x;
-    if (!pi) {
-        PatchIndex x;
-        x.h = p->patch_h;
-        long long* counts = nullptr;
-        std::vector<Alloc> tmp;
-        uint64_t tmp_bytes = 0;
-        long long* scan_tmp = nullptr;
-        int need = scan_tmp_needed(T);
-        if ((rc = dalloc_n(ctx, so->allocs, so->bytes, (size_t)T, &x.level)) ||
-            (rc = dalloc_n(ctx, so->allocs, so->bytes, (size_t)T + 1, &x.off)) ||
-            (rc = dalloc_n(ctx, tmp, tmp_bytes, (size_t)T, &counts)) ||
-            (rc = dalloc_n(ctx, tmp, tmp_bytes, (size_t)need, &scan_tmp))) {
-            free_all(ctx, tmp);
-            return rc;
-        }
-        hipError_t e = launch_patch_levels(so->dev, p->patch_h, x.level, counts, s);
-        if (e == hipSuccess) e = launch_scan_i64(counts, x.off, T, scan_tmp, need, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(&x.total, x.off + T, sizeof(long long), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        free_all(ctx, tmp);
-        if (e != hipSuccess) return fail(VPLG_EHIP, "patch index: %s", hipGetErrorString(e));
-        if (x.total > (1ll << 30)) return fail(VPLG_EINVAL, "too many patches (%lld) for patch_h", x.total);
-        so->patches.push_back(x);
-        pi = &so->patches.back();
-        so->info.device_bytes = so->bytes;
-    }
-    const long long NP = pi->total;
-    const int cap = p->k_near + p->n_far;
-    auto* v = new VplSetObj;
-    v->generated = true;
-    v->k_near = p->k_near;
-    v->n_far = p->n_far;
-    v->n_tris = T;
-    v->scene_id = scene_id;
-    v->patch_h = p->patch_h;
-    DevVpls& dv = v->dev;
-    GenBuffers& b = v->gen;
-    std::memset(&b, 0, sizeof b);
-    b.n_patches = (int)NP;
-    b.level = pi->level;
-    b.patch_off = pi->off;
-    long long n2 = 2048;
-    while (n2 < NP) n2 <<= 1;
-    int target = cap;
-    int batch = 4096;
-    while (batch < 4 * target && batch < 65536) batch <<= 1;
-    b.batch = batch;
-    b.scan_tmp_len = scan_tmp_needed((int)std::max<long long>(NP, 1));
-    size_t cap1 = cap > 0 ? (size_t)cap : 1;
-    size_t np1 = NP > 0 ? (size_t)NP : 1;
-    auto A = [&](auto** ptr, size_t n) { return dalloc_n(ctx, v->allocs, v->bytes, n, ptr); };
-    if ((rc = A(&dv.px, cap1)) || (rc = A(&dv.py, cap1)) || (rc = A(&dv.pz, cap1)) || (rc = A(&dv.nx, cap1)) ||
-        (rc = A(&dv.ny, cap1)) || (rc = A(&dv.nz, cap1)) || (rc = A(&dv.ir, cap1)) || (rc = A(&dv.ig, cap1)) ||
-        (rc = A(&dv.ib, cap1)) || (rc = A(&dv.tri, cap1)) || (rc = A(&dv.count, 1)) || (rc = A(&dv.pack, 3 * cap1)) ||
-        (rc = A(&b.pflags, np1)) ||
-        (rc = A(&b.sortbuf, (size_t)n2)) || (rc = A(&b.sorted, np1)) || (rc = A(&b.keys, np1)) ||
-        (rc = A(&b.strata, (size_t)std::max(1, p->k_near))) || (rc = A(&b.vpl_path, cap1)) ||
-        (rc = A(&b.vpl_bounce, cap1)) || (rc = A(&b.state, 1)) || (rc = A(&b.q, np1)) ||
-        (rc = A(&b.scan_out, np1 + 1)) || (rc = A(&b.stage_pos, 3 * cap1)) || (rc = A(&b.stage_flux, 3 * cap1)) ||
-        (rc = A(&b.w_count, (size_t)batch)) || (rc = A(&b.w_pos, 9 * (size_t)batch)) ||
-        (rc = A(&b.w_flux, 9 * (size_t)batch)) || (rc = A(&b.w_tri, 3 * (size_t)batch)) ||
-        (rc = A(&b.w_bounce, 3 * (size_t)batch)) || (rc = A(&b.scan_tmp, (size_t)b.scan_tmp_len))) {
+    if ((rc = patch_index(ctx, so, p->patch_h, s, &pi))) return rc;
+    VplSetObj* v = nullptr;
+    if ((rc = alloc_genset(ctx, so, scene_id, pi, p, &v))) return rc;
+    if ((rc = launch_genset(so, v, cam, p, s))) {
         release_set(ctx, v);
         return rc;
     }
-    dv.capacity = cap;
-    b.F = b.scan_out + 1;
-    CamBasis cb = cam_basis(cam);
-    GenParams gp{p->k_near, p->n_far, p->max_bounces, p->max_paths, p->d_near, p->patch_h, p->t_eps};
-    hipError_t e = launch_generate(so->dev, so->light, cb, gp, dv, b, s);
-    if (e == hipSuccess) e = launch_pack_vpls(dv, s);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&v->done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(v->done, s);
-    if (e != hipSuccess) {
-        release_set(ctx, v);
-        return fail(VPLG_EHIP, "generation launch failed: %s", hipGetErrorString(e));
-    }
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     uint64_t id = ctx->next_id++;
     ctx->sets[id] = v;
     *vplset_id = id;
@@ -587,13 +589,7 @@ int vplg_vpls_regenerate(vplg_context* ctx, uint64_t vplset_id, const vplg_camer
         return fail(VPLG_EINVAL, "regeneration must keep k_near, n_far and patch_h of the set");
     SceneObj* so = find_scene(ctx, v->scene_id);
     if (!so) return fail(VPLG_ENOTFOUND, "the scene of VPL set %llu was released", (unsigned long long)vplset_id);
-    CamBasis cb = cam_basis(cam);
-    GenParams gp{p->k_near, p->n_far, p->max_bounces, p->max_paths, p->d_near, p->patch_h, p->t_eps};
-    hipStream_t s = (hipStream_t)stream;
-    HIPCHK(launch_generate(so->dev, so->light, cb, gp, v->dev, v->gen, s));
-    HIPCHK(launch_pack_vpls(v->dev, s));
-    HIPCHK(hipEventRecord(v->done, s));
-    return VPLG_OK;
+    return launch_genset(so, v, cam, p, (hipStream_t)stream);
 }
 
 int vplg_vplset_stats(vplg_context* ctx, uint64_t vplset_id, vplg_gen_stats* out)
@@ -753,6 +749,11 @@ int vplg_vplset_release(vplg_context* ctx, uint64_t vplset_id)
     return VPLG_OK;
 }
 
+}  // extern "C"
+
+namespace vplg {
+namespace rt {
+
 static uint32_t ceil_log2(long long x)
 {
     uint32_t k = 0;
@@ -766,13 +767,13 @@ static uint32_t shape_bucket(int width, int height, int n_vpls)
     return (ceil_log2((long long)width * height) << 8) | ceil_log2(n_vpls > 0 ? n_vpls : 1);
 }
 
-static int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls)
+int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls)
 {
     auto it = ctx->tuned.find(shape_bucket(width, height, n_vpls));
     return it == ctx->tuned.end() ? 8 : it->second;
 }
 
-static int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                          float* const radiance[3], const vplg_gather_params* p, GatherArgs* a)
 {
     int rc = set_device(ctx);
@@ -787,6 +788,12 @@ static int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_i
     if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
     VplSetObj* v = find_set(ctx, vplset_id);
     if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
+    return gather_args(ctx, so, v, gb, radiance, p, a);
+}
+
+int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffer* gb, float* const radiance[3],
+                const vplg_gather_params* p, GatherArgs* a)
+{
     a->scene = so->dev;
     a->vpls = v->dev;
     a->gb = dev_gbuffer(gb);
@@ -802,6 +809,11 @@ static int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_i
     a->waves_per_tile = w;
     return VPLG_OK;
 }
+
+}  // namespace rt
+}  // namespace vplg
+
+extern "C" {
 
 int vplg_gather(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                 float* const radiance[3], const vplg_gather_params* p, void* stream)
@@ -852,6 +864,8 @@ int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t v
     return VPLG_OK;
 }
 
+}  // extern "C"
+
 static int batch_init(vplg_context* ctx)
 {
     BatchEngine& be = ctx->batch;
@@ -877,6 +891,8 @@ static int batch_init(vplg_context* ctx)
     be.ready = true;
     return VPLG_OK;
 }
+
+extern "C" {
 
 int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views, void* stream)
 {

@@ -1,0 +1,136 @@
+// Internal state of the host runtime, shared by runtime.cpp and server.cpp.
+// Not part of the ABI.
+#pragma once
+
+#include <cstdarg>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "vplg.h"
+#include "vplg_impl.h"
+
+namespace vplg {
+
+bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vector<float4>& out_tris, int* n_leaves,
+               int* max_depth, std::string& err);
+
+namespace rt {
+
+extern thread_local std::string g_err;
+int fail(int code, const char* fmt, ...);
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return ::vplg::rt::fail(VPLG_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct Alloc {
+    void* p;
+    size_t bytes;
+};
+
+struct PatchIndex {
+    double h;
+    int32_t* level;
+    long long* off;
+    long long total;
+};
+
+struct SceneObj {
+    DevScene dev;
+    DevLight light;
+    std::vector<Alloc> allocs;
+    uint64_t bytes = 0;
+    vplg_scene_info info;
+    std::vector<PatchIndex> patches;
+};
+
+struct VplSetObj {
+    DevVpls dev;
+    std::vector<Alloc> allocs;
+    uint64_t bytes = 0;
+    bool generated = false;
+    GenBuffers gen;
+    int k_near = 0;
+    int n_far = 0;
+    int n_tris = 0;
+    uint64_t scene_id = 0;
+    double patch_h = 0.0;
+    hipEvent_t done = nullptr;
+};
+
+// Persistent batched gather: device work table and view descriptors, their
+// pinned staging, and the HIP graph of (counter reset + persistent kernel).
+struct BatchEngine {
+    BatchTable* d_tab = nullptr;
+    GatherArgs* d_views = nullptr;
+    unsigned int* d_counter = nullptr;
+    BatchTable* h_tab = nullptr;
+    GatherArgs* h_views = nullptr;
+    hipEvent_t staged = nullptr;  // last use of the pinned staging
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int blocks = 0;
+    bool ready = false;
+};
+
+}  // namespace rt
+}  // namespace vplg
+
+struct vplg_context {
+    int device = 0;
+    uint64_t budget = 0, used = 0;
+    uint64_t next_id = 1;
+    std::map<uint64_t, vplg::rt::SceneObj*> scenes;
+    std::map<uint64_t, vplg::rt::VplSetObj*> sets;
+    vplg::rt::BatchEngine batch;
+    std::map<uint32_t, int> tuned;  // view-shape bucket -> waves per 8 x 8 tile
+    std::recursive_mutex mu;        // budget accounting, shared with a running server thread
+};
+
+namespace vplg {
+namespace rt {
+
+int dalloc(vplg_context* ctx, std::vector<Alloc>& list, uint64_t& acc, size_t bytes, void** out);
+template <class T>
+int dalloc_n(vplg_context* ctx, std::vector<Alloc>& list, uint64_t& acc, size_t n, T** out)
+{
+    void* p = nullptr;
+    int rc = dalloc(ctx, list, acc, n * sizeof(T), &p);
+    *out = (T*)p;
+    return rc;
+}
+void free_all(vplg_context* ctx, std::vector<Alloc>& list);
+int set_device(vplg_context* ctx);
+SceneObj* find_scene(vplg_context* ctx, uint64_t id);
+VplSetObj* find_set(vplg_context* ctx, uint64_t id);
+void release_set(vplg_context* ctx, VplSetObj* v);
+CamBasis cam_basis(const vplg_camera* c);
+int check_camera(const vplg_camera* c);
+int check_gbuffer(const vplg_gbuffer* gb);
+int check_gen_params(const vplg_gen_params* p);
+DevGBuffer dev_gbuffer(const vplg_gbuffer* gb);
+int wait_set(VplSetObj* v);
+int set_count(VplSetObj* v, int32_t* n);
+// G-buffer kernel of a resident scene (arguments already checked)
+int render_gbuffer(SceneObj* so, const vplg_camera* cam, const vplg_gbuffer* gb, hipStream_t s);
+// patch index of a scene for patch_h (first use synchronises `s`)
+int patch_index(vplg_context* ctx, SceneObj* so, double h, hipStream_t s, PatchIndex** out);
+// device bytes a generated set of this shape holds
+uint64_t genset_bytes(long long n_patches, int k_near, int n_far);
+// allocate a generated set (no launch); launch (or relaunch) its generation
+int alloc_genset(vplg_context* ctx, SceneObj* so, uint64_t scene_id, PatchIndex* pi, const vplg_gen_params* p,
+                 VplSetObj** out);
+int launch_genset(SceneObj* so, VplSetObj* v, const vplg_camera* cam, const vplg_gen_params* p, hipStream_t s);
+int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls);
+int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                  float* const radiance[3], const vplg_gather_params* p, GatherArgs* a);
+int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffer* gb, float* const radiance[3],
+                const vplg_gather_params* p, GatherArgs* a);
+
+}  // namespace rt
+}  // namespace vplg

@@ -71,6 +71,28 @@ class View(C.Structure):
                 ("radiance", C.c_void_p * 3), ("params", GatherParams)]
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_inflight", C.c_int32), ("n_streams", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("scene_id", C.c_uint64), ("camera", Camera), ("gen", GenParams), ("gather", GatherParams),
+                ("radiance", C.c_void_p * 3)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("state", C.c_int32), ("error", C.c_int32), ("submit_ns", C.c_int64), ("admit_ns", C.c_int64),
+                ("done_ns", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("cancelled", C.c_int64), ("queued", C.c_int64), ("running", C.c_int64),
+                ("peak_running", C.c_int64), ("pool_bytes", C.c_uint64), ("peak_bytes", C.c_uint64)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED, REQ_CANCELLED = 0, 1, 2, 3, 4
+
 _p = C.c_void_p
 _u64 = C.c_uint64
 _SIGS = {
@@ -102,6 +124,13 @@ _SIGS = {
     "vplg_autotune_lookup": (C.c_int, [_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     "vplg_autotune_save": (C.c_int, [_p, C.c_char_p]),
     "vplg_autotune_load": (C.c_int, [_p, C.c_char_p]),
+    "vplg_server_start": (C.c_int, [_p, C.POINTER(ServerParams), C.POINTER(_p)]),
+    "vplg_server_submit": (C.c_int, [_p, C.POINTER(Request), C.POINTER(_u64)]),
+    "vplg_server_poll": (C.c_int, [_p, _u64, C.POINTER(Timing)]),
+    "vplg_server_wait": (C.c_int, [_p, _u64, C.c_int64, C.POINTER(Timing)]),
+    "vplg_server_cancel": (C.c_int, [_p, _u64]),
+    "vplg_server_query": (C.c_int, [_p, C.POINTER(ServerStats)]),
+    "vplg_server_stop": (C.c_int, [_p]),
 }
 
 
@@ -413,3 +442,59 @@ def autotune_save(ctx, path):
 
 def autotune_load(ctx, path):
     _check(lib().vplg_autotune_load(ctx, os.fsencode(path)))
+
+
+def _timing(t):
+    return dict(state=t.state, error=t.error, submit_ns=t.submit_ns, admit_ns=t.admit_ns, done_ns=t.done_ns)
+
+
+def server_start(ctx, hbm_budget_bytes, max_inflight=8, n_streams=4):
+    prm = ServerParams(int(hbm_budget_bytes), int(max_inflight), int(n_streams))
+    h = C.c_void_p()
+    _check(lib().vplg_server_start(ctx, C.byref(prm), C.byref(h)))
+    return h
+
+
+def make_request(scene_id, camera, gen_params, radiance, gather_params=None):
+    r = Request()
+    r.scene_id = scene_id
+    r.camera = make_camera(camera)
+    r.gen = make_gen_params(gen_params)
+    gp = gather_params if isinstance(gather_params, GatherParams) else make_gather_params(gather_params or gen_params)
+    r.gather = gp
+    rp = radiance_planes(radiance)
+    for c in range(3):
+        r.radiance[c] = rp[c]
+    return r
+
+
+def server_submit(srv, request):
+    t = C.c_uint64()
+    _check(lib().vplg_server_submit(srv, C.byref(request), C.byref(t)))
+    return t.value
+
+
+def server_poll(srv, ticket):
+    t = Timing()
+    _check(lib().vplg_server_poll(srv, ticket, C.byref(t)))
+    return _timing(t)
+
+
+def server_wait(srv, ticket, timeout_ms=-1):
+    t = Timing()
+    _check(lib().vplg_server_wait(srv, ticket, int(timeout_ms), C.byref(t)))
+    return _timing(t)
+
+
+def server_cancel(srv, ticket):
+    _check(lib().vplg_server_cancel(srv, ticket))
+
+
+def server_query(srv):
+    st = ServerStats()
+    _check(lib().vplg_server_query(srv, C.byref(st)))
+    return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+
+def server_stop(srv):
+    _check(lib().vplg_server_stop(srv))
