@@ -259,20 +259,22 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
         std::memcpy(f, ints, sizeof f);
         o[3] = make_float4(f[0], f[1], f[2], f[3]);
     }
-    out_tris.resize(3 * (size_t)T);
+    out_tris.resize(kTriStride * (size_t)T);
     for (int i = 0; i < T; ++i) {
         int t = B.idx[i];
         const float* p = xyz + 9 * (size_t)t;
         float idf;
         std::memcpy(&idf, &t, sizeof idf);
-        out_tris[3 * i] = make_float4(p[0], p[1], p[2], idf);
-        float e1[3] = {p[3] - p[0], p[4] - p[1], p[5] - p[2]};
-        float e2[3] = {p[6] - p[0], p[7] - p[1], p[8] - p[2]};
-        double n[3] = {(double)e1[1] * e2[2] - (double)e1[2] * e2[1], (double)e1[2] * e2[0] - (double)e1[0] * e2[2],
-                       (double)e1[0] * e2[1] - (double)e1[1] * e2[0]};
-        double cut = kParallelTau * kParallelTau * (n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        out_tris[3 * i + 1] = make_float4(e1[0], e1[1], e1[2], 0.f);
-        out_tris[3 * i + 2] = make_float4(e2[0], e2[1], e2[2], (float)cut);
+        double e1[3] = {(double)p[3] - p[0], (double)p[4] - p[1], (double)p[5] - p[2]};
+        double e2[3] = {(double)p[6] - p[0], (double)p[7] - p[1], (double)p[8] - p[2]};
+        double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        float nf[3] = {(float)n[0], (float)n[1], (float)n[2]};
+        double cut = kParallelTau * kParallelTau *
+                     ((double)nf[0] * nf[0] + (double)nf[1] * nf[1] + (double)nf[2] * nf[2]);
+        out_tris[kTriStride * i] = make_float4(p[0], p[1], p[2], idf);
+        out_tris[kTriStride * i + 1] = make_float4(p[3], p[4], p[5], (float)cut);
+        out_tris[kTriStride * i + 2] = make_float4(p[6], p[7], p[8], 0.f);
+        out_tris[kTriStride * i + 3] = make_float4(nf[0], nf[1], nf[2], 0.f);
     }
     *n_leaves = B.n_leaves;
     *max_depth = B.max_depth;

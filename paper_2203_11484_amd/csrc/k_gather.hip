@@ -41,34 +41,81 @@ struct Counters {
     unsigned long long packets = 0, psteps = 0, plane = 0, ptris = 0;
 };
 
-// Moller-Trumbore against leaf-ordered triangle i; returns the hit parameter
-// in *t.  d2 = |d|^2: rays within kParallelTau of the triangle's plane miss.
-__device__ __forceinline__ bool tri_hit32(const float4* __restrict__ tris, int i, float ox, float oy, float oz,
-                                          float dx, float dy, float dz, float d2, float tlo, float thi, int ex0,
-                                          int ex1, float* tout, float* uout, float* vout, int* idout)
+// Per-ray set-up of the watertight ray/triangle test (Woop, Benthin and
+// Wald 2013): the dominant direction axis kz, the two others kx, ky (swapped
+// when d[kz] < 0 to keep the winding), and the shear/scale taking the ray to
+// the +z axis through the origin.
+struct WtRay {
+    float ox, oy, oz, dx, dy, dz, d2;
+    float sx, sy, sz;
+    int kx, ky, kz;
+};
+
+__device__ __forceinline__ float sel3(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
+
+__device__ __forceinline__ WtRay wt_ray(float ox, float oy, float oz, float dx, float dy, float dz)
 {
-    float4 a = tris[3 * i];
-    float4 e1 = tris[3 * i + 1];
-    float4 e2 = tris[3 * i + 2];
-    int id = __float_as_int(a.w);
-    float px = dy * e2.z - dz * e2.y;
-    float py = dz * e2.x - dx * e2.z;
-    float pz = dx * e2.y - dy * e2.x;
-    float det = e1.x * px + e1.y * py + e1.z * pz;
-    float inv = rcpf(det);
-    float tx = ox - a.x, ty = oy - a.y, tz = oz - a.z;
-    float u = (tx * px + ty * py + tz * pz) * inv;
-    float qx = ty * e1.z - tz * e1.y;
-    float qy = tz * e1.x - tx * e1.z;
-    float qz = tx * e1.y - ty * e1.x;
-    float v = (dx * qx + dy * qy + dz * qz) * inv;
-    float t = (e2.x * qx + e2.y * qy + e2.z * qz) * inv;
+    WtRay r;
+    r.ox = ox; r.oy = oy; r.oz = oz;
+    r.dx = dx; r.dy = dy; r.dz = dz;
+    r.d2 = dx * dx + dy * dy + dz * dz;
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    r.kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    r.kx = r.kz == 2 ? 0 : r.kz + 1;
+    r.ky = r.kx == 2 ? 0 : r.kx + 1;
+    const float dkz = sel3(dx, dy, dz, r.kz);
+    if (dkz < 0.f) {
+        int t = r.kx;
+        r.kx = r.ky;
+        r.ky = t;
+    }
+    r.sx = sel3(dx, dy, dz, r.kx) / dkz;
+    r.sy = sel3(dx, dy, dz, r.ky) / dkz;
+    r.sz = 1.0f / dkz;
+    return r;
+}
+
+// Watertight test of leaf-ordered triangle i (two-sided): hit iff the ray
+// crosses the closed triangle at a parameter in (tlo, thi), the triangle is
+// neither excluded (ex0, ex1) nor within kParallelTau of the ray direction.
+// Returns the parameter and the barycentric weights of B and C.
+__device__ __forceinline__ bool tri_hit32(const float4* __restrict__ tris, int i, const WtRay& r, float tlo, float thi,
+                                          int ex0, int ex1, float* tout, float* uout, float* vout, int* idout)
+{
+    const float4 q0 = tris[kTriStride * i], q1 = tris[kTriStride * i + 1], q2 = tris[kTriStride * i + 2],
+                 q3 = tris[kTriStride * i + 3];
+    const int id = __float_as_int(q0.w);
+    const float nd = q3.x * r.dx + q3.y * r.dy + q3.z * r.dz;
+    const bool steep = nd * nd > q1.w * r.d2;
+    // vertices relative to the ray origin, permuted and sheared into ray space
+    const float ax = q0.x - r.ox, ay = q0.y - r.oy, az = q0.z - r.oz;
+    const float bx = q1.x - r.ox, by = q1.y - r.oy, bz = q1.z - r.oz;
+    const float cx = q2.x - r.ox, cy = q2.y - r.oy, cz = q2.z - r.oz;
+    const float akz = sel3(ax, ay, az, r.kz), bkz = sel3(bx, by, bz, r.kz), ckz = sel3(cx, cy, cz, r.kz);
+    const float Ax = fmaf(-r.sx, akz, sel3(ax, ay, az, r.kx)), Ay = fmaf(-r.sy, akz, sel3(ax, ay, az, r.ky));
+    const float Bx = fmaf(-r.sx, bkz, sel3(bx, by, bz, r.kx)), By = fmaf(-r.sy, bkz, sel3(bx, by, bz, r.ky));
+    const float Cx = fmaf(-r.sx, ckz, sel3(cx, cy, cz, r.kx)), Cy = fmaf(-r.sy, ckz, sel3(cx, cy, cz, r.ky));
+    // edge functions: products rounded separately, so the two triangles of a
+    // shared edge compute exact negatives of each other
+    float U = __fsub_rn(__fmul_rn(Cx, By), __fmul_rn(Cy, Bx));
+    float V = __fsub_rn(__fmul_rn(Ax, Cy), __fmul_rn(Ay, Cx));
+    float W = __fsub_rn(__fmul_rn(Bx, Ay), __fmul_rn(By, Ax));
+    if (U == 0.f || V == 0.f || W == 0.f) {
+        // exact sign on an edge: float products are exact in double
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    const bool mixed = (U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f);
+    const float det = U + V + W;
+    const float T = U * (r.sz * akz) + V * (r.sz * bkz) + W * (r.sz * ckz);
+    const float inv = rcpf(det);
+    const float t = T * inv;
     *tout = t;
-    *uout = u;
-    *vout = v;
+    *uout = V * inv;
+    *vout = W * inv;
     *idout = id;
-    return u >= 0.f && v >= 0.f && u + v <= 1.f && t > tlo && t < thi && id != ex0 && id != ex1 &&
-           det * det > e2.w * d2;
+    return !mixed && det != 0.f && steep && t > tlo && t < thi && id != ex0 && id != ex1;
 }
 
 struct SlabRay {
@@ -107,7 +154,7 @@ __device__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz,
     r.ox = ox * r.ix;
     r.oy = oy * r.iy;
     r.oz = oz * r.iz;
-    const float d2 = dx * dx + dy * dy + dz * dz;
+    const WtRay wr = wt_ray(ox, oy, oz, dx, dy, dz);
     const float4* __restrict__ nodes = sc.nodes;
     const float4* __restrict__ tris = sc.tris;
     bool alive = act;
@@ -133,7 +180,7 @@ __device__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz,
                     int id;
                     if (COUNT && h0 && alive) cnt.tris++;
                     if (COUNT && lane == 0) cnt.ptris++;
-                    bool hit = tri_hit32(tris, i, ox, oy, oz, dx, dy, dz, d2, tlo, thi, ex0, ex1, &t, &u, &v, &id);
+                    bool hit = tri_hit32(tris, i, wr, tlo, thi, ex0, ex1, &t, &u, &v, &id);
                     if (h0 && hit) alive = false;
                 }
             }
@@ -146,7 +193,7 @@ __device__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz,
                     int id;
                     if (COUNT && h1 && alive) cnt.tris++;
                     if (COUNT && lane == 0) cnt.ptris++;
-                    bool hit = tri_hit32(tris, i, ox, oy, oz, dx, dy, dz, d2, tlo, thi, ex0, ex1, &t, &u, &v, &id);
+                    bool hit = tri_hit32(tris, i, wr, tlo, thi, ex0, ex1, &t, &u, &v, &id);
                     if (h1 && hit) alive = false;
                 }
             }
@@ -418,7 +465,7 @@ __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
     r.ox = ox * r.ix;
     r.oy = oy * r.iy;
     r.oz = oz * r.iz;
-    const float d2 = dx * dx + dy * dy + dz * dz;
+    const WtRay wr = wt_ray(ox, oy, oz, dx, dy, dz);
     const float4* __restrict__ nodes = a.scene.nodes;
     const float4* __restrict__ tris = a.scene.tris;
     int* stack = s_stack + tid;
@@ -441,8 +488,7 @@ __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
                 for (int i = first; i < first + count; ++i) {
                     float t, u, v;
                     int id;
-                    bool ok = tri_hit32(tris, i, ox, oy, oz, dx, dy, dz, d2, 0.0f, __builtin_inff(), -2, -2, &t, &u,
-                                        &v, &id);
+                    bool ok = tri_hit32(tris, i, wr, 0.0f, __builtin_inff(), -2, -2, &t, &u, &v, &id);
                     if (ok && (t < best || (t == best && id < bid))) {
                         best = t; bu = u; bv = v; bid = id; bi = i;
                     }
@@ -475,10 +521,11 @@ __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
         for (int c = 0; c < 3; ++c) { a.pos[c][p] = 0.f; a.nrm[c][p] = 0.f; a.alb[c][p] = 0.f; }
         return;
     }
-    float4 v0 = tris[3 * bi], e1 = tris[3 * bi + 1], e2 = tris[3 * bi + 2];
-    a.pos[0][p] = v0.x + bu * e1.x + bv * e2.x;
-    a.pos[1][p] = v0.y + bu * e1.y + bv * e2.y;
-    a.pos[2][p] = v0.z + bu * e1.z + bv * e2.z;
+    const float4 va = tris[kTriStride * bi], vb = tris[kTriStride * bi + 1], vc = tris[kTriStride * bi + 2];
+    const float bw = 1.0f - bu - bv;
+    a.pos[0][p] = bw * va.x + bu * vb.x + bv * vc.x;
+    a.pos[1][p] = bw * va.y + bu * vb.y + bv * vc.y;
+    a.pos[2][p] = bw * va.z + bu * vb.z + bv * vc.z;
     float4 n = a.scene.normals[bid];
     a.nrm[0][p] = n.x; a.nrm[1][p] = n.y; a.nrm[2][p] = n.z;
     a.alb[0][p] = a.scene.albedo[3 * bid];

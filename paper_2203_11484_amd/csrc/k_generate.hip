@@ -249,7 +249,7 @@ __device__ bool visible64(const DevScene& s, d3 x, int tx, d3 y, int ty, double 
             if (!h) continue;
             if (k[ch] > 0) {
                 for (int i = c[ch]; i < c[ch] + k[ch]; ++i) {
-                    int t = __float_as_int(s.tris[3 * i].w);
+                    int t = __float_as_int(s.tris[kTriStride * i].w);
                     double tt, u, v;
                     if (t == tx || t == ty) continue;
                     if (tri64(s, t, x, d, &tt, &u, &v) && tt > lo && tt < hi) return false;
@@ -285,7 +285,7 @@ __device__ int closest64(const DevScene& s, d3 o, d3 d, double tmin, int ex, boo
             if (!h) continue;
             if (k[ch] > 0) {
                 for (int i = c[ch]; i < c[ch] + k[ch]; ++i) {
-                    int t = __float_as_int(s.tris[3 * i].w);
+                    int t = __float_as_int(s.tris[kTriStride * i].w);
                     double tt, u, v;
                     if (t == ex || (skip_emit && (s.flags[t] & 1))) continue;
                     if (tri64(s, t, o, d, &tt, &u, &v) && tt > tmin) {

@@ -21,14 +21,17 @@ namespace vplg {
 // leaf-ordered triangle array; count == 0 and c >= 0 is an inner node; c < 0
 // is an absent child (its box is empty).  Node 0 is the root.
 //
-// Leaf-ordered triangles, three float4 each: (A, id), (B - A, 0),
-// (C - A, cut), id = the original triangle index (bit pattern of an int) and
-// cut = (kParallelTau |(B - A) x (C - A)|)^2.  The FP32 ray tests treat a ray
-// whose direction makes an angle below kParallelTau with the triangle's plane
-// as missing it: there |det| is at the level of FP32 rounding and the
-// barycentrics are noise, and any such ray that does cross the triangle is a
-// grazing pair whose visibility either answer serves.
+// Leaf-ordered triangles, four float4 each (one 64-byte scalar load):
+// (A, id), (B, cut), (C, 0), (n, 0) with id = the original triangle index
+// (bit pattern of an int), n = (B - A) x (C - A) and cut = (kParallelTau |n|)^2.
+// The FP32 ray tests are watertight (shared vertices are transformed
+// identically for every triangle a ray tests, so a ray through a shared edge
+// cannot slip between its two triangles) and treat a ray whose direction
+// makes an angle below kParallelTau with the triangle's plane as missing it:
+// there the projected triangle is degenerate at FP32 rounding, and any such
+// ray that does cross the triangle is a grazing pair either answer serves.
 constexpr double kParallelTau = 2e-5;
+constexpr int kTriStride = 4;
 constexpr int kMaxDepth = 48;   // builder guarantees depth <= kMaxDepth - 1
 constexpr int kStack = 48;      // per-lane traversal stack entries
 

@@ -127,6 +127,17 @@ def test_gather_room20k_sampled(vplg, ctx):
     print(f"room20k: {nd} grazing disagreements of {n} pairs")
 
 
+def test_gather_room200k_sampled(vplg, ctx):
+    """202k-triangle room at its full 1920x1080 size and 16,384 VPLs, in the bench's launch configuration;
+    96 sampled pixels checked pair by pair (1.6M pairs)."""
+    sc = scenes.make_scene("room200k")
+    S, gbo, vp, _ = _oracle_inputs(sc)
+    rng = np.random.default_rng(9)
+    pixels = np.sort(rng.choice(1920 * 1080, 96, replace=False))
+    nd, n = _check_gather(vplg, ctx, sc, S, gbo, vp, pixels, sc["params"], "room200k")
+    print(f"room200k: {nd} grazing disagreements of {n} cast pairs")
+
+
 def test_gather_deterministic(vplg, ctx):
     sc = scenes.make_scene("cornell", width=64, height=48)
     S, gbo, vp, _ = _oracle_inputs(sc)
@@ -187,9 +198,10 @@ def test_gbuffer_parity(vplg, ctx):
         vplg.scene_release(ctx, sid)
 
 
-@pytest.mark.parametrize("name", ["cornell", "room20k"])
+@pytest.mark.parametrize("name", ["cornell", "room20k", "room200k"])
 def test_generation_parity(vplg, ctx, name):
-    sc = scenes.make_scene(name, width=64, height=64)
+    """Every integer output of the generation bit-exact at the workloads' full sizes."""
+    sc = scenes.make_scene(name)
     S = orc.Scene.from_dict(sc)
     ref = S.generate(sc["camera"], sc["light"], sc["params"])
     sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
