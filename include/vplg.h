@@ -90,7 +90,7 @@ typedef struct {
  *   tri_flags  host uint8 [n_tris]: bit 0 = emitter (never receives VPLs).
  *   light      host pointer, copied.
  * On success *scene_id names the resident scene.  The call synchronises the
- * stream before it returns.  EINVAL: n_tris < 1 or > 2^27, null pointer,
+ * stream before it returns.  EINVAL: n_tris < 1 or > 2^25, null pointer,
  * non-finite vertex, unknown light kind.  EBUDGET / ENOMEM: no room. */
 int vplg_scene_upload(vplg_context* ctx, const float* tri_xyz, const float* tri_albedo, const uint8_t* tri_flags,
                       int32_t n_tris, const vplg_light* light, void* stream, uint64_t* scene_id);

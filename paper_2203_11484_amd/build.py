@@ -20,8 +20,11 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-I", INCLUDE,
 # decisions whose operation order must be kept exactly (no contraction)
 SOURCES = [
     # the FP32 ray kernels never see NaN box or triangle inputs (degenerate
-    # determinants fail the parallel-ray cut), so min/max need no NaN quieting
-    ("k_gather.hip", ["-fno-honor-nans"]),
+    # determinants fail the parallel-ray cut), so min/max need no NaN quieting;
+    # no contraction: the watertight edge functions need separately rounded
+    # products (fused forms are written out as fmaf); the packet traversal's
+    # wave-uniform branches stay plain scalar branches (no structurisation)
+    ("k_gather.hip", ["-fno-honor-nans", "-ffp-contract=off", "-mllvm", "-structurizecfg-skip-uniform-regions=true"]),
     ("k_generate.hip", ["-ffp-contract=off"]),
     ("bvh_build.cpp", []),
     ("runtime.cpp", ["-ffp-contract=off"]),

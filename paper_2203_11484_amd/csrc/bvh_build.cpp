@@ -208,7 +208,8 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
         return false;
     }
     // flatten: device nodes are the inner build nodes; a leaf-only tree gets
-    // an inner root with one absent child
+    // an inner root whose two children are that one leaf, so that every
+    // device node has two present children
     std::vector<int> dev_of(B.nodes.size(), -1);
     std::vector<int> order;
     if (B.nodes[root].count > 0) {
@@ -228,12 +229,6 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
     float pad = 1e-6f * std::max(maxabs, 1.0f);
     out_nodes.assign(4 * order.size(), make_float4(0, 0, 0, 0));
     auto child = [&](int c, float* lo, float* hi, int* ref, int* cnt) {
-        if (c < 0) {
-            for (int k = 0; k < 3; ++k) { lo[k] = 1.0f; hi[k] = -1.0f; }
-            *ref = -1;
-            *cnt = 0;
-            return;
-        }
         const BNode& n = B.nodes[c];
         for (int k = 0; k < 3; ++k) {
             lo[k] = pad_down(n.box.lo[k], pad);
@@ -244,7 +239,7 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
     };
     for (size_t i = 0; i < order.size(); ++i) {
         int l, r;
-        if (order[i] < 0) { l = root; r = -1; }
+        if (order[i] < 0) { l = root; r = root; }
         else { l = B.nodes[order[i]].left; r = B.nodes[order[i]].right; }
         float lo0[3], hi0[3], lo1[3], hi1[3];
         int c0, c1, k0, k1;

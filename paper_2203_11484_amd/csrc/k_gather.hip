@@ -28,6 +28,26 @@ constexpr float kInvPi = 0.318309886183790671538f;
 
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// One 64-byte node or triangle record, fetched by a single load (a scalar
+// s_load_dwordx16 when the index is wave-uniform).  Scenes hold at most 2^25
+// triangles, so a record's byte offset fits in 32 bits.
+typedef float Rec16 __attribute__((ext_vector_type(16)));
+
+struct Rec {
+    float4 q0, q1, q2, q3;
+};
+
+__device__ __forceinline__ Rec load_rec(const float4* __restrict__ base, int idx)
+{
+    const Rec16 v = *(const Rec16*)((const char*)base + (size_t)((unsigned)idx << 6));
+    Rec r;
+    r.q0 = make_float4(v.s0, v.s1, v.s2, v.s3);
+    r.q1 = make_float4(v.s4, v.s5, v.s6, v.s7);
+    r.q2 = make_float4(v.s8, v.s9, v.sa, v.sb);
+    r.q3 = make_float4(v.sc, v.sd, v.se, v.sf);
+    return r;
+}
+
 __device__ __forceinline__ float safe_inv(float d)
 {
     // A zero direction component would turn the slab test into 0 * inf; a
@@ -77,15 +97,16 @@ __device__ __forceinline__ WtRay wt_ray(float ox, float oy, float oz, float dx, 
 
 // Watertight test of leaf-ordered triangle i (two-sided): hit iff the ray
 // crosses the closed triangle at a parameter in (tlo, thi), the triangle is
-// neither excluded (ex0, ex1) nor within kParallelTau of the ray direction.
-// Returns the parameter and the barycentric weights of B and C.
-__device__ __forceinline__ bool tri_hit32(const float4* __restrict__ tris, int i, const WtRay& r, float tlo, float thi,
-                                          int ex0, int ex1, float* tout, float* uout, float* vout, int* idout)
+// not excluded (ex0) nor within kParallelTau of the ray direction.  Returns
+// the parameter and the barycentric weights of B and C.  The file is built
+// without floating-point contraction, so every product below is rounded on
+// its own unless written as fmaf.
+__device__ __forceinline__ bool tri_hit32(const Rec& rec, const WtRay& r, float tlo, float thi, int ex0, float* tout,
+                                          float* uout, float* vout, int* idout)
 {
-    const float4 q0 = tris[kTriStride * i], q1 = tris[kTriStride * i + 1], q2 = tris[kTriStride * i + 2],
-                 q3 = tris[kTriStride * i + 3];
+    const float4 q0 = rec.q0, q1 = rec.q1, q2 = rec.q2, q3 = rec.q3;
     const int id = __float_as_int(q0.w);
-    const float nd = q3.x * r.dx + q3.y * r.dy + q3.z * r.dz;
+    const float nd = fmaf(q3.z, r.dz, fmaf(q3.y, r.dy, q3.x * r.dx));
     const bool steep = nd * nd > q1.w * r.d2;
     // vertices relative to the ray origin, permuted and sheared into ray space
     const float ax = q0.x - r.ox, ay = q0.y - r.oy, az = q0.z - r.oz;
@@ -97,54 +118,158 @@ __device__ __forceinline__ bool tri_hit32(const float4* __restrict__ tris, int i
     const float Cx = fmaf(-r.sx, ckz, sel3(cx, cy, cz, r.kx)), Cy = fmaf(-r.sy, ckz, sel3(cx, cy, cz, r.ky));
     // edge functions: products rounded separately, so the two triangles of a
     // shared edge compute exact negatives of each other
-    float U = __fsub_rn(__fmul_rn(Cx, By), __fmul_rn(Cy, Bx));
-    float V = __fsub_rn(__fmul_rn(Ax, Cy), __fmul_rn(Ay, Cx));
-    float W = __fsub_rn(__fmul_rn(Bx, Ay), __fmul_rn(By, Ax));
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
     if (U == 0.f || V == 0.f || W == 0.f) {
         // exact sign on an edge: float products are exact in double
         U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
         V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
         W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
     }
-    const bool mixed = (U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f);
+    const bool mixed = fminf(fminf(U, V), W) < 0.f && fmaxf(fmaxf(U, V), W) > 0.f;
     const float det = U + V + W;
-    const float T = U * (r.sz * akz) + V * (r.sz * bkz) + W * (r.sz * ckz);
+    const float T = fmaf(W, r.sz * ckz, fmaf(V, r.sz * bkz, U * (r.sz * akz)));
     const float inv = rcpf(det);
     const float t = T * inv;
     *tout = t;
     *uout = V * inv;
     *vout = W * inv;
     *idout = id;
-    return !mixed && det != 0.f && steep && t > tlo && t < thi && id != ex0 && id != ex1;
+    return !mixed && det != 0.f && steep && t > tlo && t < thi && id != ex0;
 }
 
 struct SlabRay {
     float ix, iy, iz, ox, oy, oz;  // inverse direction and origin * inverse
 };
 
+// Slab test of both child boxes of a node.  OCT < 8: every ray of the packet
+// has direction signs OCT (bit a set: inverse direction on axis a is
+// negative), so the entry plane of each slab is known; OCT == 8: any signs.
+template <int OCT>
 __device__ __forceinline__ void child_boxes(const float4& n0, const float4& n1, const float4& n2, const SlabRay& r,
                                             float tlo, float thi, float* lo0, float* hi0, float* lo1, float* hi1)
 {
-    float a0 = fmaf(n0.x, r.ix, -r.ox), a1 = fmaf(n0.y, r.ix, -r.ox);
-    float b0 = fmaf(n0.z, r.iy, -r.oy), b1 = fmaf(n0.w, r.iy, -r.oy);
-    float c0 = fmaf(n2.x, r.iz, -r.oz), c1 = fmaf(n2.y, r.iz, -r.oz);
-    *lo0 = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), tlo));
-    *hi0 = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), thi));
-    float d0 = fmaf(n1.x, r.ix, -r.ox), d1 = fmaf(n1.y, r.ix, -r.ox);
-    float e0 = fmaf(n1.z, r.iy, -r.oy), e1 = fmaf(n1.w, r.iy, -r.oy);
-    float f0 = fmaf(n2.z, r.iz, -r.oz), f1 = fmaf(n2.w, r.iz, -r.oz);
-    *lo1 = fmaxf(fmaxf(fminf(d0, d1), fminf(e0, e1)), fmaxf(fminf(f0, f1), tlo));
-    *hi1 = fminf(fminf(fmaxf(d0, d1), fmaxf(e0, e1)), fminf(fmaxf(f0, f1), thi));
+    if constexpr (OCT < 8) {
+        constexpr bool nx = OCT & 1, ny = OCT & 2, nz = OCT & 4;
+        const float a0 = fmaf(nx ? n0.y : n0.x, r.ix, -r.ox), a1 = fmaf(nx ? n0.x : n0.y, r.ix, -r.ox);
+        const float b0 = fmaf(ny ? n0.w : n0.z, r.iy, -r.oy), b1 = fmaf(ny ? n0.z : n0.w, r.iy, -r.oy);
+        const float c0 = fmaf(nz ? n2.y : n2.x, r.iz, -r.oz), c1 = fmaf(nz ? n2.x : n2.y, r.iz, -r.oz);
+        *lo0 = fmaxf(fmaxf(a0, b0), fmaxf(c0, tlo));
+        *hi0 = fminf(fminf(a1, b1), fminf(c1, thi));
+        const float d0 = fmaf(nx ? n1.y : n1.x, r.ix, -r.ox), d1 = fmaf(nx ? n1.x : n1.y, r.ix, -r.ox);
+        const float e0 = fmaf(ny ? n1.w : n1.z, r.iy, -r.oy), e1 = fmaf(ny ? n1.z : n1.w, r.iy, -r.oy);
+        const float f0 = fmaf(nz ? n2.w : n2.z, r.iz, -r.oz), f1 = fmaf(nz ? n2.z : n2.w, r.iz, -r.oz);
+        *lo1 = fmaxf(fmaxf(d0, e0), fmaxf(f0, tlo));
+        *hi1 = fminf(fminf(d1, e1), fminf(f1, thi));
+    } else {
+        const float a0 = fmaf(n0.x, r.ix, -r.ox), a1 = fmaf(n0.y, r.ix, -r.ox);
+        const float b0 = fmaf(n0.z, r.iy, -r.oy), b1 = fmaf(n0.w, r.iy, -r.oy);
+        const float c0 = fmaf(n2.x, r.iz, -r.oz), c1 = fmaf(n2.y, r.iz, -r.oz);
+        *lo0 = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), tlo));
+        *hi0 = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), thi));
+        const float d0 = fmaf(n1.x, r.ix, -r.ox), d1 = fmaf(n1.y, r.ix, -r.ox);
+        const float e0 = fmaf(n1.z, r.iy, -r.oy), e1 = fmaf(n1.w, r.iy, -r.oy);
+        const float f0 = fmaf(n2.z, r.iz, -r.oz), f1 = fmaf(n2.w, r.iz, -r.oz);
+        *lo1 = fmaxf(fmaxf(fminf(d0, d1), fminf(e0, e1)), fmaxf(fminf(f0, f1), tlo));
+        *hi1 = fminf(fminf(fmaxf(d0, d1), fmaxf(e0, e1)), fminf(fmaxf(f0, f1), thi));
+    }
 }
 
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+__device__ __forceinline__ bool lane_bit(unsigned long long m, int lane) { return (m >> lane) & 1ull; }
+
+// Any-hit test of the packet lanes in `enter` (a subset of `alive`) against
+// the triangles [first, first + count) of one leaf.  Returns `alive` with
+// the blocked lanes cleared; stops early once every entering lane is blocked.
+template <bool COUNT>
+__device__ __forceinline__ unsigned long long leaf_any_hit(const float4* __restrict__ tris, int first, int count,
+                                                           const WtRay& wr, float tlo, float thi, int ex0, int ex1,
+                                                           unsigned long long enter, unsigned long long alive, int lane,
+                                                           Counters& cnt)
+{
+    for (int i = first; i < first + count; ++i) {
+        if (COUNT && lane_bit(enter & alive, lane)) cnt.tris++;
+        if (COUNT && lane == 0) cnt.ptris++;
+        const Rec rec = load_rec(tris, i);
+        float t, u, v;
+        int id;
+        const bool hit = tri_hit32(rec, wr, tlo, thi, ex0, &t, &u, &v, &id);
+        unsigned long long blocked = ballot(hit) & enter;
+        if (id == ex1) blocked = 0;  // the VPL's own triangle
+        alive &= ~blocked;
+        if ((alive & enter) == 0) break;
+    }
+    return alive;
+}
+
+// BVH walk of one packet (see packet_visible) with slab-test variant OCT.
+template <bool COUNT, int OCT>
+__device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                                         const SlabRay& r, const WtRay& wr, bool act, float tlo, float thi, int ex0,
+                                         int ex1, int lane, Counters& cnt)
+{
+    unsigned long long alive = ballot(act);
+    int slot = 0;
+    int sp = 0;
+    int node = 0;
+    while (true) {
+        const Rec nd = load_rec(nodes, node);
+        const float4 n0 = nd.q0, n1 = nd.q1, n2 = nd.q2, n3f = nd.q3;
+        const int c0 = __float_as_int(n3f.x), c1 = __float_as_int(n3f.y);
+        const int k0 = __float_as_int(n3f.z), k1 = __float_as_int(n3f.w);
+        if (COUNT && lane_bit(alive, lane)) cnt.nodes++;
+        if (COUNT && lane == 0) cnt.psteps++;
+        float lo0, hi0, lo1, hi1;
+        child_boxes<OCT>(n0, n1, n2, r, tlo, thi, &lo0, &hi0, &lo1, &hi1);
+        unsigned long long b0 = ballot(lo0 <= hi0) & alive;
+        unsigned long long b1 = ballot(lo1 <= hi1) & alive;
+        if ((k0 | k1) > 0) {
+            // a leaf child is tested at once and never entered
+            if (k0 > 0) {
+                if (b0) alive = leaf_any_hit<COUNT>(tris, c0, k0, wr, tlo, thi, ex0, ex1, b0, alive, lane, cnt);
+                b0 = 0;
+            }
+            if (k1 > 0) {
+                if (b1 & alive) alive = leaf_any_hit<COUNT>(tris, c1, k1, wr, tlo, thi, ex0, ex1, b1, alive, lane, cnt);
+                b1 = 0;
+            }
+            if (alive == 0) break;
+            b0 &= alive;
+            b1 &= alive;
+        }
+        if (b0) {
+            if (b1) {
+                // both: the nearer first (as seen by the lowest lane that
+                // enters both), the other pushed
+                const int l = __builtin_ctzll((b0 & b1) | (1ull << 63));
+                const bool first0 = __builtin_amdgcn_readlane(lo0 <= lo1 ? 1 : 0, l) != 0;
+                slot = lane == sp ? (first0 ? c1 : c0) : slot;
+                ++sp;
+                node = first0 ? c0 : c1;
+            } else {
+                node = c0;
+            }
+        } else if (b1) {
+            node = c1;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = __builtin_amdgcn_readlane(slot, sp);
+        }
+    }
+    return lane_bit(alive, lane);
+}
+
 // Any-hit test of a wave's 64 segments o + s d, s in (tlo, thi), walked as
 // one packet.  `act` marks the lanes with a ray; ex0 (per lane) and ex1
 // (wave-uniform) are the excluded host triangles.  Returns, per lane,
-// whether its ray is active and unblocked.
+// whether its ray is active and unblocked.  All control is wave-uniform:
+// `alive` is the mask of unblocked lanes, and the traversal stack holds
+// entry i in lane i of `slot`.
 template <bool COUNT>
-__device__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz, float dx, float dy, float dz,
+__device__ __forceinline__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz, float dx, float dy, float dz,
                                bool act, float tlo, float thi, int ex0, int ex1, int lane, Counters& cnt)
 {
     SlabRay r;
@@ -157,71 +282,23 @@ __device__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz,
     const WtRay wr = wt_ray(ox, oy, oz, dx, dy, dz);
     const float4* __restrict__ nodes = sc.nodes;
     const float4* __restrict__ tris = sc.tris;
-    bool alive = act;
-    int slot = 0;  // stack entry `lane` of the wave-uniform stack
-    int sp = 0;
-    int node = 0;
-    while (true) {
-        const float4* nd = nodes + 4 * node;
-        float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3f = nd[3];
-        int c0 = __float_as_int(n3f.x), c1 = __float_as_int(n3f.y);
-        int k0 = __float_as_int(n3f.z), k1 = __float_as_int(n3f.w);
-        if (COUNT && alive) cnt.nodes++;
-        if (COUNT && lane == 0) cnt.psteps++;
-        float lo0, hi0, lo1, hi1;
-        child_boxes(n0, n1, n2, r, tlo, thi, &lo0, &hi0, &lo1, &hi1);
-        bool h0 = alive && lo0 <= hi0 && c0 >= 0;
-        bool h1 = alive && lo1 <= hi1 && c1 >= 0;
-        unsigned long long b0 = ballot(h0), b1 = ballot(h1);
-        if (k0 > 0) {
-            if (b0) {
-                for (int i = c0; i < c0 + k0; ++i) {
-                    float t, u, v;
-                    int id;
-                    if (COUNT && h0 && alive) cnt.tris++;
-                    if (COUNT && lane == 0) cnt.ptris++;
-                    bool hit = tri_hit32(tris, i, wr, tlo, thi, ex0, ex1, &t, &u, &v, &id);
-                    if (h0 && hit) alive = false;
-                }
-            }
-            h0 = false;
-        }
-        if (k1 > 0) {
-            if (b1) {
-                for (int i = c1; i < c1 + k1; ++i) {
-                    float t, u, v;
-                    int id;
-                    if (COUNT && h1 && alive) cnt.tris++;
-                    if (COUNT && lane == 0) cnt.ptris++;
-                    bool hit = tri_hit32(tris, i, wr, tlo, thi, ex0, ex1, &t, &u, &v, &id);
-                    if (h1 && hit) alive = false;
-                }
-            }
-            h1 = false;
-        }
-        unsigned long long live = ballot(alive);
-        if (live == 0) return false;
-        b0 = ballot(h0 && alive);
-        b1 = ballot(h1 && alive);
-        if (b0 && b1) {
-            // near child first, as seen by the lowest lane that enters both
-            int l = __builtin_ctzll(b0 & b1 ? (b0 & b1) : live);
-            bool first0 = __builtin_amdgcn_readlane(lo0 <= lo1 ? 1 : 0, l) != 0;
-            int far_c = first0 ? c1 : c0;
-            slot = lane == sp ? far_c : slot;
-            ++sp;
-            node = first0 ? c0 : c1;
-        } else if (b0) {
-            node = c0;
-        } else if (b1) {
-            node = c1;
-        } else {
-            if (sp == 0) break;
-            --sp;
-            node = __builtin_amdgcn_readlane(slot, sp);
-        }
+    ex1 = __builtin_amdgcn_readfirstlane(ex1);  // uniform by contract; keeps the leaf loop scalar
+    // one sign pattern for every active lane: the slab entry planes are fixed
+    const unsigned long long am = ballot(act);
+    const unsigned long long sx = ballot(r.ix < 0.f) & am, sy = ballot(r.iy < 0.f) & am, sz = ballot(r.iz < 0.f) & am;
+    const bool uni = (sx == 0 || sx == am) && (sy == 0 || sy == am) && (sz == 0 || sz == am);
+    const int oct = uni ? (sx ? 1 : 0) | (sy ? 2 : 0) | (sz ? 4 : 0) : 8;
+    switch (oct) {
+    case 0: return traverse<COUNT, 0>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
+    case 1: return traverse<COUNT, 1>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
+    case 2: return traverse<COUNT, 2>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
+    case 3: return traverse<COUNT, 3>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
+    case 4: return traverse<COUNT, 4>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
+    case 5: return traverse<COUNT, 5>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
+    case 6: return traverse<COUNT, 6>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
+    case 7: return traverse<COUNT, 7>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
+    default: return traverse<COUNT, 8>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
     }
-    return alive;
 }
 
 // Pixel of lane `tid` in a 16 x 16 tile: each wave64 owns an 8 x 8 quadrant.
@@ -253,7 +330,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 // only on (tile, nw), never on what else runs in the launch.  All waves of
 // the group must call this together; `sync` is a barrier over the group.
 template <bool COUNT, class Sync>
-__device__ void gather_tile(const GatherArgs& a, int tile, int wave, int nw, int lane, float (*red)[3][64],
+__device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int wave, int nw, int lane, float (*red)[3][64],
                             Counters& cnt, unsigned long long& pairs, Sync sync)
 {
     const int W = a.gb.width, H = a.gb.height;
@@ -354,7 +431,7 @@ __global__ __launch_bounds__(kGatherMaxThreads) void k_gather(GatherArgs a)
 {
     __shared__ float s_red[kGatherMaxWaves][3][64];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     const int tiles = ((a.gb.width + 7) >> 3) * ((a.gb.height + 7) >> 3);
     Counters cnt;
@@ -374,7 +451,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_gather_batch(const BatchTa
     __shared__ float s_red[kBatchWaves][3][64];
     __shared__ int s_item;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n_views = tab->n_views;
     const int total = tab->prefix[n_views];
     Counters cnt;
@@ -382,7 +459,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_gather_batch(const BatchTa
     while (true) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);  // an LDS value is uniform here
         __syncthreads();
         if (item >= total) break;
         int lo = 0, hi = n_views;  // view: last v with prefix[v] <= item
@@ -478,9 +555,9 @@ __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
         int c0 = __float_as_int(n3f.x), c1 = __float_as_int(n3f.y);
         int k0 = __float_as_int(n3f.z), k1 = __float_as_int(n3f.w);
         float lo0, hi0, lo1, hi1;
-        child_boxes(n0, n1, n2, r, 0.0f, best, &lo0, &hi0, &lo1, &hi1);
-        bool h0 = lo0 <= hi0 && c0 >= 0;
-        bool h1 = lo1 <= hi1 && c1 >= 0;
+        child_boxes<8>(n0, n1, n2, r, 0.0f, best, &lo0, &hi0, &lo1, &hi1);
+        bool h0 = lo0 <= hi0;
+        bool h1 = lo1 <= hi1;
         for (int c = 0; c < 2; ++c) {
             bool h = c == 0 ? h0 : h1;
             int first = c == 0 ? c0 : c1, count = c == 0 ? k0 : k1;
@@ -488,7 +565,7 @@ __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
                 for (int i = first; i < first + count; ++i) {
                     float t, u, v;
                     int id;
-                    bool ok = tri_hit32(tris, i, wr, 0.0f, __builtin_inff(), -2, -2, &t, &u, &v, &id);
+                    bool ok = tri_hit32(load_rec(tris, i), wr, 0.0f, __builtin_inff(), -2, &t, &u, &v, &id);
                     if (ok && (t < best || (t == best && id < bid))) {
                         best = t; bu = u; bv = v; bid = id; bi = i;
                     }

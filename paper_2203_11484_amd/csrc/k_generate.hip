@@ -243,7 +243,6 @@ __device__ bool visible64(const DevScene& s, d3 x, int tx, d3 y, int ty, double 
         int c[2] = {__float_as_int(n3f.x), __float_as_int(n3f.y)};
         int k[2] = {__float_as_int(n3f.z), __float_as_int(n3f.w)};
         for (int ch = 0; ch < 2; ++ch) {
-            if (c[ch] < 0) continue;
             bool h = ch == 0 ? box64(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, x, d, lo, hi)
                              : box64(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, x, d, lo, hi);
             if (!h) continue;
@@ -279,7 +278,6 @@ __device__ int closest64(const DevScene& s, d3 o, d3 d, double tmin, int ex, boo
         int c[2] = {__float_as_int(n3f.x), __float_as_int(n3f.y)};
         int k[2] = {__float_as_int(n3f.z), __float_as_int(n3f.w)};
         for (int ch = 0; ch < 2; ++ch) {
-            if (c[ch] < 0) continue;
             bool h = ch == 0 ? box64(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, o, d, tmin, bt)
                              : box64(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, o, d, tmin, bt);
             if (!h) continue;

@@ -238,7 +238,9 @@ int vplg_scene_upload(vplg_context* ctx, const float* tri_xyz, const float* tri_
     int rc = set_device(ctx);
     if (rc) return rc;
     if (!tri_xyz || !tri_albedo || !tri_flags || !light || !scene_id) return fail(VPLG_EINVAL, "null argument");
-    if (n_tris < 1 || n_tris > (1 << 27)) return fail(VPLG_EINVAL, "n_tris %d out of range", n_tris);
+    // at most 2^25 triangles: node and triangle records (64 bytes each, fewer
+    // than 2 n_tris nodes) are then addressed by 32-bit byte offsets
+    if (n_tris < 1 || n_tris > (1 << 25)) return fail(VPLG_EINVAL, "n_tris %d out of range", n_tris);
     if (light->kind != 0 && light->kind != 1) return fail(VPLG_EINVAL, "unknown light kind %d", light->kind);
     for (size_t i = 0; i < 9 * (size_t)n_tris; ++i)
         if (!std::isfinite(tri_xyz[i])) return fail(VPLG_EINVAL, "non-finite vertex coordinate at %zu", i);

@@ -18,8 +18,9 @@ namespace vplg {
 //   n2 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
 //   n3 = (int c0, int c1, int c0_count, int c1_count)
 // A child with count > 0 is a leaf holding triangles [c, c + count) of the
-// leaf-ordered triangle array; count == 0 and c >= 0 is an inner node; c < 0
-// is an absent child (its box is empty).  Node 0 is the root.
+// leaf-ordered triangle array; count == 0 is an inner node.  Both children
+// are always present (a scene that fits one leaf gets a root whose two
+// children are that leaf).  Node 0 is the root.
 //
 // Leaf-ordered triangles, four float4 each (one 64-byte scalar load):
 // (A, id), (B, cut), (C, 0), (n, 0) with id = the original triangle index
