@@ -266,6 +266,7 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
         float nf[3] = {(float)n[0], (float)n[1], (float)n[2]};
         double cut = kParallelTau * kParallelTau *
                      ((double)nf[0] * nf[0] + (double)nf[1] * nf[1] + (double)nf[2] * nf[2]);
+        if (!((float)cut > 0.f)) cut = HUGE_VAL;  // degenerate: never hit
         out_tris[kTriStride * i] = make_float4(p[0], p[1], p[2], idf);
         out_tris[kTriStride * i + 1] = make_float4(p[3], p[4], p[5], (float)cut);
         out_tris[kTriStride * i + 2] = make_float4(p[6], p[7], p[8], 0.f);

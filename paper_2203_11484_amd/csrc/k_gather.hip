@@ -62,12 +62,15 @@ struct Counters {
 };
 
 // Per-ray set-up of the watertight ray/triangle test (Woop, Benthin and
-// Wald 2013): the dominant direction axis kz, the two others kx, ky (swapped
-// when d[kz] < 0 to keep the winding), and the shear/scale taking the ray to
-// the +z axis through the origin.
+// Wald 2013): the dominant direction axis kz, the two others kx, ky in cyclic
+// order, and the shear/scale taking the ray to the +z axis through the
+// origin.  The test is two-sided, so the kx/ky swap the paper uses to keep
+// the winding for d[kz] < 0 is left out: it would only negate all three edge
+// functions, the determinant and T exactly.
 struct WtRay {
-    float ox, oy, oz, dx, dy, dz, d2;
+    float ox, oy, oz;
     float sx, sy, sz;
+    float q;  // |d|^2 / d[kz]^2: scales the parallel-ray cut to the determinant
     int kx, ky, kz;
 };
 
@@ -77,37 +80,38 @@ __device__ __forceinline__ WtRay wt_ray(float ox, float oy, float oz, float dx, 
 {
     WtRay r;
     r.ox = ox; r.oy = oy; r.oz = oz;
-    r.dx = dx; r.dy = dy; r.dz = dz;
-    r.d2 = dx * dx + dy * dy + dz * dz;
     const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
     r.kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
     r.kx = r.kz == 2 ? 0 : r.kz + 1;
     r.ky = r.kx == 2 ? 0 : r.kx + 1;
     const float dkz = sel3(dx, dy, dz, r.kz);
-    if (dkz < 0.f) {
-        int t = r.kx;
-        r.kx = r.ky;
-        r.ky = t;
-    }
     r.sx = sel3(dx, dy, dz, r.kx) / dkz;
     r.sy = sel3(dx, dy, dz, r.ky) / dkz;
     r.sz = 1.0f / dkz;
+    r.q = fmaf(r.sy, r.sy, fmaf(r.sx, r.sx, 1.0f));
     return r;
 }
 
-// Watertight test of leaf-ordered triangle i (two-sided): hit iff the ray
-// crosses the closed triangle at a parameter in (tlo, thi), the triangle is
-// not excluded (ex0) nor within kParallelTau of the ray direction.  Returns
-// the parameter and the barycentric weights of B and C.  The file is built
-// without floating-point contraction, so every product below is rounded on
-// its own unless written as fmaf.
-__device__ __forceinline__ bool tri_hit32(const Rec& rec, const WtRay& r, float tlo, float thi, int ex0, float* tout,
-                                          float* uout, float* vout, int* idout)
+// Watertight test of one leaf-ordered triangle record (two-sided).  The ray
+// crosses the closed triangle iff the edge functions U, V, W are not of mixed
+// sign and their sum (the determinant) is non-zero; the hit parameter is
+// T / det.  The determinant equals d . n / d[kz] (n = (B - A) x (C - A)), so
+// the parallel-ray cut |d . n| > kParallelTau |d| |n| reads
+// det^2 > cut q with the stored cut = (kParallelTau |n|)^2 (infinite for a
+// degenerate triangle).  The file is built without floating-point
+// contraction, so every product below is rounded on its own unless written
+// as fmaf.
+struct TriEval {
+    float U, V, W, det, t, inv;
+    bool steep;
+    int id;
+};
+
+__device__ __forceinline__ TriEval tri_eval(const Rec& rec, const WtRay& r)
 {
-    const float4 q0 = rec.q0, q1 = rec.q1, q2 = rec.q2, q3 = rec.q3;
-    const int id = __float_as_int(q0.w);
-    const float nd = fmaf(q3.z, r.dz, fmaf(q3.y, r.dy, q3.x * r.dx));
-    const bool steep = nd * nd > q1.w * r.d2;
+    const float4 q0 = rec.q0, q1 = rec.q1, q2 = rec.q2;
+    TriEval e;
+    e.id = __float_as_int(q0.w);
     // vertices relative to the ray origin, permuted and sheared into ray space
     const float ax = q0.x - r.ox, ay = q0.y - r.oy, az = q0.z - r.oz;
     const float bx = q1.x - r.ox, by = q1.y - r.oy, bz = q1.z - r.oz;
@@ -127,16 +131,28 @@ __device__ __forceinline__ bool tri_hit32(const Rec& rec, const WtRay& r, float 
         V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
         W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
     }
-    const bool mixed = fminf(fminf(U, V), W) < 0.f && fmaxf(fmaxf(U, V), W) > 0.f;
-    const float det = U + V + W;
+    e.U = U;
+    e.V = V;
+    e.W = W;
+    e.det = U + V + W;
     const float T = fmaf(W, r.sz * ckz, fmaf(V, r.sz * bkz, U * (r.sz * akz)));
-    const float inv = rcpf(det);
-    const float t = T * inv;
-    *tout = t;
-    *uout = V * inv;
-    *vout = W * inv;
-    *idout = id;
-    return !mixed && det != 0.f && steep && t > tlo && t < thi && id != ex0;
+    e.inv = rcpf(e.det);
+    e.t = T * e.inv;
+    e.steep = e.det * e.det > q1.w * r.q;
+    return e;
+}
+
+// Per-lane hit test for the closest-hit walk: parameter in (tlo, thi).
+__device__ __forceinline__ bool tri_hit32(const Rec& rec, const WtRay& r, float tlo, float thi, float* tout,
+                                          float* uout, float* vout, int* idout)
+{
+    const TriEval e = tri_eval(rec, r);
+    const bool mixed = fminf(fminf(e.U, e.V), e.W) < 0.f && fmaxf(fmaxf(e.U, e.V), e.W) > 0.f;
+    *tout = e.t;
+    *uout = e.V * e.inv;
+    *vout = e.W * e.inv;
+    *idout = e.id;
+    return !mixed && e.det != 0.f && e.steep && e.t > tlo && e.t < thi;
 }
 
 struct SlabRay {
@@ -192,12 +208,14 @@ __device__ __forceinline__ unsigned long long leaf_any_hit(const float4* __restr
     for (int i = first; i < first + count; ++i) {
         if (COUNT && lane_bit(enter & alive, lane)) cnt.tris++;
         if (COUNT && lane == 0) cnt.ptris++;
-        const Rec rec = load_rec(tris, i);
-        float t, u, v;
-        int id;
-        const bool hit = tri_hit32(rec, wr, tlo, thi, ex0, &t, &u, &v, &id);
-        unsigned long long blocked = ballot(hit) & enter;
-        if (id == ex1) blocked = 0;  // the VPL's own triangle
+        const TriEval e = tri_eval(load_rec(tris, i), wr);
+        // lanes whose segment is blocked: the masks of the single conditions
+        // combine on the scalar unit
+        const unsigned long long inside = ballot(fminf(fminf(e.U, e.V), e.W) >= 0.f) |
+                                          ballot(fmaxf(fmaxf(e.U, e.V), e.W) <= 0.f);
+        unsigned long long blocked = inside & ballot(e.det != 0.f) & ballot(e.steep) & ballot(e.t > tlo) &
+                                     ballot(e.t < thi) & ballot(e.id != ex0) & enter;
+        if (e.id == ex1) blocked = 0;  // the VPL's own triangle
         alive &= ~blocked;
         if ((alive & enter) == 0) break;
     }
@@ -565,7 +583,7 @@ __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
                 for (int i = first; i < first + count; ++i) {
                     float t, u, v;
                     int id;
-                    bool ok = tri_hit32(load_rec(tris, i), wr, 0.0f, __builtin_inff(), -2, &t, &u, &v, &id);
+                    bool ok = tri_hit32(load_rec(tris, i), wr, 0.0f, __builtin_inff(), &t, &u, &v, &id);
                     if (ok && (t < best || (t == best && id < bid))) {
                         best = t; bu = u; bv = v; bid = id; bi = i;
                     }

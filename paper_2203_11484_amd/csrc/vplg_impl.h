@@ -24,7 +24,8 @@ namespace vplg {
 //
 // Leaf-ordered triangles, four float4 each (one 64-byte scalar load):
 // (A, id), (B, cut), (C, 0), (n, 0) with id = the original triangle index
-// (bit pattern of an int), n = (B - A) x (C - A) and cut = (kParallelTau |n|)^2.
+// (bit pattern of an int), n = (B - A) x (C - A) and cut = (kParallelTau |n|)^2
+// (+inf for a degenerate triangle, whose cut would round to zero).
 // The FP32 ray tests are watertight (shared vertices are transformed
 // identically for every triangle a ray tests, so a ray through a shared edge
 // cannot slip between its two triangles) and treat a ray whose direction
