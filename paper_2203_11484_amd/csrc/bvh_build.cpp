@@ -52,6 +52,7 @@ struct BNode {
     int left = -1, right = -1;
     int first = 0, count = 0;  // leaf iff count > 0
     int depth = 0;
+    int axis = 0;  // split axis of an inner node: the left child holds the lower centroids
 };
 
 struct Builder {
@@ -91,6 +92,7 @@ struct Builder {
         if (ext[1] > ext[axis]) axis = 1;
         if (ext[2] > ext[axis]) axis = 2;
         int mid = -1;
+        int split_axis = axis;
         if (ext[axis] <= 0.f) {
             if (n <= kLeafMax) return make_leaf(begin, end, b, depth);
             mid = begin + n / 2;  // identical centroids: split the list
@@ -149,9 +151,11 @@ struct Builder {
                     return bi <= best_split;
                 });
                 mid = (int)(it - idx.begin());
+                split_axis = best_axis;
             }
             if (mid <= begin || mid >= end) {
                 mid = begin + n / 2;
+                split_axis = axis;
                 std::nth_element(idx.begin() + begin, idx.begin() + mid, idx.begin() + end, [&](int a, int c) {
                     float ka = cen[3 * a + axis], kc = cen[3 * c + axis];
                     return ka < kc || (ka == kc && a < c);
@@ -161,6 +165,7 @@ struct Builder {
         BNode node;
         node.box = b;
         node.depth = depth;
+        node.axis = split_axis;
         nodes.push_back(node);
         int me = (int)nodes.size() - 1;
         int l = build(begin, mid, depth + 1);
@@ -229,6 +234,7 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
     float pad = 1e-6f * std::max(maxabs, 1.0f);
     out_nodes.assign(4 * order.size(), make_float4(0, 0, 0, 0));
     auto child = [&](int c, float* lo, float* hi, int* ref, int* cnt) {
+        // leaf counts share one word: the builder keeps them far below 2^16
         const BNode& n = B.nodes[c];
         for (int k = 0; k < 3; ++k) {
             lo[k] = pad_down(n.box.lo[k], pad);
@@ -239,8 +245,9 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
     };
     for (size_t i = 0; i < order.size(); ++i) {
         int l, r;
+        int axis = 0;
         if (order[i] < 0) { l = root; r = root; }
-        else { l = B.nodes[order[i]].left; r = B.nodes[order[i]].right; }
+        else { l = B.nodes[order[i]].left; r = B.nodes[order[i]].right; axis = B.nodes[order[i]].axis; }
         float lo0[3], hi0[3], lo1[3], hi1[3];
         int c0, c1, k0, k1;
         child(l, lo0, hi0, &c0, &k0);
@@ -250,7 +257,7 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
         o[1] = make_float4(lo1[0], hi1[0], lo1[1], hi1[1]);
         o[2] = make_float4(lo0[2], hi0[2], lo1[2], hi1[2]);
         float f[4];
-        int ints[4] = {c0, c1, k0, k1};
+        int ints[4] = {c0, c1, k0 | (k1 << 16), axis};
         std::memcpy(f, ints, sizeof f);
         o[3] = make_float4(f[0], f[1], f[2], f[3]);
     }

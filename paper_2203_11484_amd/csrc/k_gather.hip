@@ -85,9 +85,9 @@ __device__ __forceinline__ WtRay wt_ray(float ox, float oy, float oz, float dx, 
     r.kx = r.kz == 2 ? 0 : r.kz + 1;
     r.ky = r.kx == 2 ? 0 : r.kx + 1;
     const float dkz = sel3(dx, dy, dz, r.kz);
-    r.sx = sel3(dx, dy, dz, r.kx) / dkz;
-    r.sy = sel3(dx, dy, dz, r.ky) / dkz;
-    r.sz = 1.0f / dkz;
+    r.sz = rcpf(dkz);
+    r.sx = sel3(dx, dy, dz, r.kx) * r.sz;
+    r.sy = sel3(dx, dy, dz, r.ky) * r.sz;
     r.q = fmaf(r.sy, r.sy, fmaf(r.sx, r.sx, 1.0f));
     return r;
 }
@@ -213,8 +213,9 @@ __device__ __forceinline__ unsigned long long leaf_any_hit(const float4* __restr
         // combine on the scalar unit
         const unsigned long long inside = ballot(fminf(fminf(e.U, e.V), e.W) >= 0.f) |
                                           ballot(fmaxf(fmaxf(e.U, e.V), e.W) <= 0.f);
-        unsigned long long blocked = inside & ballot(e.det != 0.f) & ballot(e.steep) & ballot(e.t > tlo) &
-                                     ballot(e.t < thi) & ballot(e.id != ex0) & enter;
+        // steep implies det != 0 (det^2 > cut q > 0)
+        unsigned long long blocked = inside & ballot(e.steep) & ballot(e.t > tlo) & ballot(e.t < thi) &
+                                     ballot(e.id != ex0) & enter;
         if (e.id == ex1) blocked = 0;  // the VPL's own triangle
         alive &= ~blocked;
         if ((alive & enter) == 0) break;
@@ -226,7 +227,7 @@ __device__ __forceinline__ unsigned long long leaf_any_hit(const float4* __restr
 template <bool COUNT, int OCT>
 __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                          const SlabRay& r, const WtRay& wr, bool act, float tlo, float thi, int ex0,
-                                         int ex1, int lane, Counters& cnt)
+                                         int ex1, int oct, int lane, Counters& cnt)
 {
     unsigned long long alive = ballot(act);
     int slot = 0;
@@ -236,15 +237,16 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
         const Rec nd = load_rec(nodes, node);
         const float4 n0 = nd.q0, n1 = nd.q1, n2 = nd.q2, n3f = nd.q3;
         const int c0 = __float_as_int(n3f.x), c1 = __float_as_int(n3f.y);
-        const int k0 = __float_as_int(n3f.z), k1 = __float_as_int(n3f.w);
+        const int kk = __float_as_int(n3f.z), axis = __float_as_int(n3f.w);
         if (COUNT && lane_bit(alive, lane)) cnt.nodes++;
         if (COUNT && lane == 0) cnt.psteps++;
         float lo0, hi0, lo1, hi1;
         child_boxes<OCT>(n0, n1, n2, r, tlo, thi, &lo0, &hi0, &lo1, &hi1);
         unsigned long long b0 = ballot(lo0 <= hi0) & alive;
         unsigned long long b1 = ballot(lo1 <= hi1) & alive;
-        if ((k0 | k1) > 0) {
+        if (kk != 0) {
             // a leaf child is tested at once and never entered
+            const int k0 = kk & 0xffff, k1 = kk >> 16;
             if (k0 > 0) {
                 if (b0) alive = leaf_any_hit<COUNT>(tris, c0, k0, wr, tlo, thi, ex0, ex1, b0, alive, lane, cnt);
                 b0 = 0;
@@ -259,13 +261,12 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
         }
         if (b0) {
             if (b1) {
-                // both: the nearer first (as seen by the lowest lane that
-                // enters both), the other pushed
-                const int l = __builtin_ctzll((b0 & b1) | (1ull << 63));
-                const bool first0 = __builtin_amdgcn_readlane(lo0 <= lo1 ? 1 : 0, l) != 0;
-                slot = lane == sp ? (first0 ? c1 : c0) : slot;
+                // both: the child on the near side of the split plane for
+                // the packet's direction signs first, the other pushed
+                const bool first1 = (oct >> axis) & 1;
+                slot = lane == sp ? (first1 ? c0 : c1) : slot;
                 ++sp;
-                node = first0 ? c0 : c1;
+                node = first1 ? c1 : c0;
             } else {
                 node = c0;
             }
@@ -306,16 +307,20 @@ __device__ __forceinline__ bool packet_visible(const DevScene& sc, float ox, flo
     const unsigned long long sx = ballot(r.ix < 0.f) & am, sy = ballot(r.iy < 0.f) & am, sz = ballot(r.iz < 0.f) & am;
     const bool uni = (sx == 0 || sx == am) && (sy == 0 || sy == am) && (sz == 0 || sz == am);
     const int oct = uni ? (sx ? 1 : 0) | (sy ? 2 : 0) | (sz ? 4 : 0) : 8;
+    // child order: the direction signs of the packet, or of its first active lane
+    const int lead = __builtin_ctzll(am | (1ull << 63));
+    const int ord = uni ? oct
+                        : (int)(((sx >> lead) & 1) | (((sy >> lead) & 1) << 1) | (((sz >> lead) & 1) << 2));
     switch (oct) {
-    case 0: return traverse<COUNT, 0>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
-    case 1: return traverse<COUNT, 1>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
-    case 2: return traverse<COUNT, 2>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
-    case 3: return traverse<COUNT, 3>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
-    case 4: return traverse<COUNT, 4>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
-    case 5: return traverse<COUNT, 5>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
-    case 6: return traverse<COUNT, 6>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
-    case 7: return traverse<COUNT, 7>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
-    default: return traverse<COUNT, 8>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, lane, cnt);
+    case 0: return traverse<COUNT, 0>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
+    case 1: return traverse<COUNT, 1>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
+    case 2: return traverse<COUNT, 2>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
+    case 3: return traverse<COUNT, 3>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
+    case 4: return traverse<COUNT, 4>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
+    case 5: return traverse<COUNT, 5>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
+    case 6: return traverse<COUNT, 6>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
+    case 7: return traverse<COUNT, 7>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
+    default: return traverse<COUNT, 8>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
     }
 }
 
@@ -571,7 +576,8 @@ __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
     while (true) {
         float4 n0 = nodes[4 * node], n1 = nodes[4 * node + 1], n2 = nodes[4 * node + 2], n3f = nodes[4 * node + 3];
         int c0 = __float_as_int(n3f.x), c1 = __float_as_int(n3f.y);
-        int k0 = __float_as_int(n3f.z), k1 = __float_as_int(n3f.w);
+        const int kk = __float_as_int(n3f.z);
+        int k0 = kk & 0xffff, k1 = kk >> 16;
         float lo0, hi0, lo1, hi1;
         child_boxes<8>(n0, n1, n2, r, 0.0f, best, &lo0, &hi0, &lo1, &hi1);
         bool h0 = lo0 <= hi0;

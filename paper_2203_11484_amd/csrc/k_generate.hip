@@ -241,7 +241,8 @@ __device__ bool visible64(const DevScene& s, d3 x, int tx, d3 y, int ty, double 
         const float4* n = s.nodes + 4 * node;
         float4 n0 = n[0], n1 = n[1], n2 = n[2], n3f = n[3];
         int c[2] = {__float_as_int(n3f.x), __float_as_int(n3f.y)};
-        int k[2] = {__float_as_int(n3f.z), __float_as_int(n3f.w)};
+        const int kk = __float_as_int(n3f.z);
+        int k[2] = {kk & 0xffff, kk >> 16};
         for (int ch = 0; ch < 2; ++ch) {
             bool h = ch == 0 ? box64(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, x, d, lo, hi)
                              : box64(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, x, d, lo, hi);
@@ -276,7 +277,8 @@ __device__ int closest64(const DevScene& s, d3 o, d3 d, double tmin, int ex, boo
         const float4* n = s.nodes + 4 * node;
         float4 n0 = n[0], n1 = n[1], n2 = n[2], n3f = n[3];
         int c[2] = {__float_as_int(n3f.x), __float_as_int(n3f.y)};
-        int k[2] = {__float_as_int(n3f.z), __float_as_int(n3f.w)};
+        const int kk = __float_as_int(n3f.z);
+        int k[2] = {kk & 0xffff, kk >> 16};
         for (int ch = 0; ch < 2; ++ch) {
             bool h = ch == 0 ? box64(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, o, d, tmin, bt)
                              : box64(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, o, d, tmin, bt);
