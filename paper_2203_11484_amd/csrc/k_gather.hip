@@ -30,16 +30,28 @@ __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x)
 
 // One 64-byte node or triangle record, fetched by a single load (a scalar
 // s_load_dwordx16 when the index is wave-uniform).  Scenes hold at most 2^25
-// triangles, so a record's byte offset fits in 32 bits.
+// triangles, so a record's byte offset fits in 32 bits.  Scene and VPL
+// records are read through the constant address space: no kernel here writes
+// them, and saying so lets the compiler use scalar loads even where the
+// kernel's own stores (a persistent loop's outputs) precede the load.
 typedef float Rec16 __attribute__((ext_vector_type(16)));
+#define VPLG_CONST __attribute__((address_space(4)))
 
 struct Rec {
     float4 q0, q1, q2, q3;
 };
 
+typedef float F4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 load_c4(const float4* __restrict__ p, int i)
+{
+    const F4v v = ((const VPLG_CONST F4v*)p)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ Rec load_rec(const float4* __restrict__ base, int idx)
 {
-    const Rec16 v = *(const Rec16*)((const char*)base + (size_t)((unsigned)idx << 6));
+    const Rec16 v = *(const VPLG_CONST Rec16*)((const VPLG_CONST char*)base + (size_t)((unsigned)idx << 6));
     Rec r;
     r.q0 = make_float4(v.s0, v.s1, v.s2, v.s3);
     r.q1 = make_float4(v.s4, v.s5, v.s6, v.s7);
@@ -382,7 +394,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int w
                 const int k = base + j * nw;
                 if (k >= M) break;
                 if (COUNT && active) pairs++;
-                float4 v0 = vp[3 * k], v1 = vp[3 * k + 1];
+                const float4 v0 = load_c4(vp, 3 * k), v1 = load_c4(vp, 3 * k + 1);
                 float dx = v0.x - x, dy = v0.y - y, dz = v0.z - z;
                 float cp = nx * dx + ny * dy + nz * dz;
                 float ck = -(v1.x * dx + v1.y * dy + v1.z * dz);
@@ -401,7 +413,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& a, int tile, int w
                 bool vis = packet_visible<COUNT>(a.scene, x, y, z, dx, dy, dz, act, tlo, thi, tp, __float_as_int(v0.w),
                                                  lane, cnt);
                 if (vis) {
-                    float4 v2 = vp[3 * k + 2];
+                    const float4 v2 = load_c4(vp, 3 * k + 2);
                     pr = fmaf(v2.x, g, pr);
                     pg = fmaf(v2.y, g, pg);
                     pb = fmaf(v2.z, g, pb);
@@ -467,7 +479,7 @@ __global__ __launch_bounds__(kGatherMaxThreads) void k_gather(GatherArgs a)
 // claims work items from a device counter until none is left (every
 // workgroup reaches the exit).  Item i of view v covers tiles
 // [j * g, (j + 1) * g) with g = kBatchWaves / w_v tile groups of w_v waves.
-__global__ __launch_bounds__(64 * kBatchWaves) void k_gather_batch(const BatchTable* __restrict__ tab,
+__global__ __launch_bounds__(64 * kBatchWaves) __attribute__((amdgpu_waves_per_eu(8))) void k_gather_batch(const BatchTable* __restrict__ tab,
                                                                     const GatherArgs* __restrict__ views,
                                                                     unsigned int* __restrict__ counter)
 {
@@ -532,7 +544,7 @@ __global__ __launch_bounds__(BLOCK) void k_vis_dump(VisDumpArgs a)
         for (int b = 0; b < 32; ++b) {
             int k = w * 32 + b;
             if (k >= M) break;
-            float4 v0 = vp[3 * k];
+            const float4 v0 = load_c4(vp, 3 * k);
             bool vis = false;
             if (ballot(ok) != 0)
                 vis = packet_visible<false>(a.scene, x, y, z, v0.x - x, v0.y - y, v0.z - z, ok, a.t_eps,
