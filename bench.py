@@ -20,10 +20,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published)
-# algorithmic FLOPs (FMA = 2): per pair of the shading formula, and per cast
-# shadow ray its setup, per visited BVH2 node (two slab tests) and per
-# Moller-Trumbore triangle test
-FLOP_PAIR, FLOP_RAY, FLOP_NODE, FLOP_TRI = 27, 6, 24, 44
+# algorithmic FLOPs (FMA = 2; min, max and compares not counted): per pair of
+# the shading formula; per cast shadow ray its slab set-up (3 reciprocals, 3
+# products) and watertight set-up (reciprocal, 2 shear products, |d|^2/d_kz^2);
+# per visited BVH2 node (two slab tests of 6 FMAs); per watertight triangle
+# test (9 differences, 6 shear FMAs, 3 edge functions, determinant, T, t and
+# the parallel cut)
+FLOP_PAIR, FLOP_RAY, FLOP_NODE, FLOP_TRI = 27, 13, 24, 44
 
 
 def measured_traffic(workload):
