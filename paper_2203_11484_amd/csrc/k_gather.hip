@@ -22,7 +22,6 @@ constexpr int BLOCK = 256;              // 4 wave64 per workgroup (G-buffer, dum
 constexpr int kGatherMaxWaves = 16;     // waves per gather workgroup (VPL slices of one tile)
 constexpr int kGatherMaxThreads = 64 * kGatherMaxWaves;
 constexpr int kChunk = 16;              // VPLs per first-level partial sum of a wave
-constexpr int kXcds = 8;                // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kBatchWaves = kBatchBlockWaves;  // waves per persistent workgroup
 constexpr float kInvPi = 0.318309886183790671538f;
 
@@ -344,19 +343,6 @@ __device__ __forceinline__ void tile_pixel(int tid, int bx, int by, int* px, int
     *py = by * 16 + (w >> 1) * 8 + (lane >> 3);
 }
 
-// Logical tile of a workgroup.  Workgroups are dealt to the 8 XCDs round
-// robin; renumbering them so that each XCD gets one contiguous band of tiles
-// keeps the rays of neighbouring tiles, and the BVH nodes they touch, in the
-// same L2.
-__device__ __forceinline__ int xcd_tile(int b, int n)
-{
-    const int per = (n + kXcds - 1) / kXcds;
-    const int xcd = b % kXcds, idx = b / kXcds;
-    const int full = n - (per - 1) * kXcds;  // XCDs that own `per` tiles (the rest own per - 1)
-    int t = xcd < full ? xcd * per + idx : full * per + (xcd - full) * (per - 1) + idx;
-    return t;
-}
-
 // Gather of one 8 x 8 pixel tile by a group of `nw` waves (wave `wave` of
 // the group takes k = wave, wave + nw, ...), each wave tracing its shadow
 // rays as one packet.  Per wave the terms are summed in chunks of kChunk
@@ -460,19 +446,44 @@ struct BlockSync {
     __device__ void operator()() const { __syncthreads(); }
 };
 
-// One workgroup per 8 x 8 pixel tile (all its waves on that tile).
+// Persistent gather of one view: each workgroup of w waves (one VPL slice
+// each) claims 8 x 8 tiles from a device counter until none is left, so the
+// tiles' uneven costs spread over all CUs of all XCDs (a fixed tile per
+// workgroup leaves whole XCDs idle: the hardware deals workgroups to the XCDs
+// round robin, whatever their cost).  Every workgroup reaches the exit.
 template <bool COUNT>
-__global__ __launch_bounds__(kGatherMaxThreads) void k_gather(GatherArgs a)
+__device__ __forceinline__ void gather_persistent(const GatherArgs& a, unsigned int* __restrict__ counter)
 {
     __shared__ float s_red[kGatherMaxWaves][3][64];
+    __shared__ int s_item;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     const int tiles = ((a.gb.width + 7) >> 3) * ((a.gb.height + 7) >> 3);
     Counters cnt;
     unsigned long long pairs = 0;
-    gather_tile<COUNT>(a, xcd_tile(blockIdx.x, tiles), wave, nw, lane, s_red, cnt, pairs, BlockSync());
+    while (true) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int tile = __builtin_amdgcn_readfirstlane(s_item);  // an LDS value is uniform here
+        __syncthreads();
+        if (tile >= tiles) break;
+        gather_tile<COUNT>(a, tile, wave, nw, lane, s_red, cnt, pairs, BlockSync());
+    }
     flush_counters<COUNT>(a.counters, cnt, pairs, lane);
+}
+
+// The plain gather is held to 8 waves per SIMD (its few scalar spills cost
+// less than a lost wave); the instrumented one keeps its registers.
+__global__ __launch_bounds__(kGatherMaxThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_gather(
+    GatherArgs a, unsigned int* __restrict__ counter)
+{
+    gather_persistent<false>(a, counter);
+}
+
+__global__ __launch_bounds__(kGatherMaxThreads) void k_gather_counted(GatherArgs a, unsigned int* __restrict__ counter)
+{
+    gather_persistent<true>(a, counter);
 }
 
 // Persistent gather over many views.  Each workgroup of kBatchWaves waves
@@ -665,16 +676,25 @@ hipError_t launch_pack_vpls(const DevVpls& v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const GatherArgs& a, bool counted, hipStream_t s)
+hipError_t gather_occupancy(int waves, bool counted, int* blocks_per_cu)
+{
+    if (waves < 1 || waves > kGatherMaxWaves || (waves & (waves - 1))) return hipErrorInvalidValue;
+    return counted ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gather_counted, 64 * waves, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gather, 64 * waves, 0);
+}
+
+hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counter, int blocks, hipStream_t s)
 {
     const int tiles = ((a.gb.width + 7) / 8) * ((a.gb.height + 7) / 8);
-    int waves = a.waves_per_tile;
-    if (waves < 1 || waves > kGatherMaxWaves || (waves & (waves - 1))) return hipErrorInvalidValue;
-    dim3 grid(tiles), block(64 * waves);
+    const int waves = a.waves_per_tile;
+    if (waves < 1 || waves > kGatherMaxWaves || (waves & (waves - 1)) || !counter || blocks < 1)
+        return hipErrorInvalidValue;
+    dim3 grid(blocks < tiles ? blocks : tiles), block(64 * waves);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
     if (counted)
-        hipLaunchKernelGGL(k_gather<true>, grid, block, 0, s, a);
+        hipLaunchKernelGGL(k_gather_counted, grid, block, 0, s, a, counter);
     else
-        hipLaunchKernelGGL(k_gather<false>, grid, block, 0, s, a);
+        hipLaunchKernelGGL(k_gather, grid, block, 0, s, a, counter);
     return hipGetLastError();
 }
 

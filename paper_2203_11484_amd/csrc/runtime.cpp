@@ -220,6 +220,7 @@ int vplg_context_destroy(vplg_context* ctx)
     if (be.d_counter) (void)hipFree(be.d_counter);
     if (be.h_tab) (void)hipHostFree(be.h_tab);
     if (be.h_views) (void)hipHostFree(be.h_views);
+    for (auto& kv : ctx->stream_counters) (void)hipFree(kv.second);
     delete ctx;
     return VPLG_OK;
 }
@@ -812,6 +813,32 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
     return VPLG_OK;
 }
 
+int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s)
+{
+    unsigned int* counter = nullptr;
+    int blocks = 0;
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        auto it = ctx->stream_counters.find((void*)s);
+        if (it == ctx->stream_counters.end()) {
+            HIPCHK(hipMalloc(&counter, sizeof(unsigned int)));
+            ctx->stream_counters[(void*)s] = counter;
+        } else {
+            counter = it->second;
+        }
+        if (ctx->cus == 0) HIPCHK(hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        const int lw = __builtin_ctz((unsigned)a.waves_per_tile);
+        int& per_cu = ctx->gather_blocks[counted ? 1 : 0][lw];
+        if (per_cu == 0) {
+            HIPCHK(gather_occupancy(a.waves_per_tile, counted, &per_cu));
+            if (per_cu < 1) per_cu = 1;
+        }
+        blocks = ctx->cus * per_cu;
+    }
+    HIPCHK(launch_gather(a, counted, counter, blocks, s));
+    return VPLG_OK;
+}
+
 }  // namespace rt
 }  // namespace vplg
 
@@ -823,8 +850,7 @@ int vplg_gather(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const 
     GatherArgs a;
     int rc = gather_common(ctx, scene_id, vplset_id, gb, radiance, p, &a);
     if (rc) return rc;
-    HIPCHK(launch_gather(a, false, (hipStream_t)stream));
-    return VPLG_OK;
+    return run_gather(ctx, a, false, (hipStream_t)stream);
 }
 
 int vplg_gather_counted(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
@@ -835,8 +861,7 @@ int vplg_gather_counted(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id
     if (rc) return rc;
     if (!counters) return fail(VPLG_EINVAL, "null counters");
     a.counters = (unsigned long long*)counters;
-    HIPCHK(launch_gather(a, true, (hipStream_t)stream));
-    return VPLG_OK;
+    return run_gather(ctx, a, true, (hipStream_t)stream);
 }
 
 int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
@@ -969,16 +994,17 @@ int vplg_autotune(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, cons
         }
         n_vpls = a.vpls.capacity;
         float ms = 0.f;
-        hipError_t e = launch_gather(a, false, s);  // warm
-        if (e == hipSuccess) e = hipEventRecord(e0, s);
-        if (e == hipSuccess) e = launch_gather(a, false, s);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
+        rc = run_gather(ctx, a, false, s);  // warm
+        hipError_t e = hipSuccess;
+        if (!rc) e = hipEventRecord(e0, s);
+        if (!rc && e == hipSuccess) rc = run_gather(ctx, a, false, s);
+        if (!rc && e == hipSuccess) e = hipEventRecord(e1, s);
+        if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+        if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (rc || e != hipSuccess) {
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
-            return fail(VPLG_EHIP, "autotune: %s", hipGetErrorString(e));
+            return rc ? rc : fail(VPLG_EHIP, "autotune: %s", hipGetErrorString(e));
         }
         if (ms < best_ms) {
             best_ms = ms;

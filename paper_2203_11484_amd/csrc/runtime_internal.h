@@ -89,6 +89,11 @@ struct vplg_context {
     std::map<uint64_t, vplg::rt::VplSetObj*> sets;
     vplg::rt::BatchEngine batch;
     std::map<uint32_t, int> tuned;  // view-shape bucket -> waves per 8 x 8 tile
+    // tile counter of the persistent single-view gather, one device word per
+    // stream (launches on one stream are ordered, so they may share it)
+    std::map<void*, unsigned int*> stream_counters;
+    int cus = 0;                      // compute units of the device
+    int gather_blocks[2][5] = {};     // [counted][log2 waves]: resident workgroups per CU, 0 = not queried
     std::recursive_mutex mu;        // budget accounting, shared with a running server thread
 };
 
@@ -131,6 +136,8 @@ int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, cons
                   float* const radiance[3], const vplg_gather_params* p, GatherArgs* a);
 int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffer* gb, float* const radiance[3],
                 const vplg_gather_params* p, GatherArgs* a);
+// launch the persistent single-view gather of `a` on `s` (its stream's tile counter, resident grid)
+int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s);
 
 }  // namespace rt
 }  // namespace vplg

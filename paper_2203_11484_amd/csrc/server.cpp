@@ -218,7 +218,7 @@ int launch(vplg_server* s, ReqObj* q)
     if ((rc = launch_genset(so, v, &r.camera, &r.gen, st))) return rc;
     GatherArgs a;
     if ((rc = gather_args(s->ctx, so, v, &gb, r.radiance, &r.gather, &a))) return rc;
-    if (launch_gather(a, false, st) != hipSuccess) return VPLG_EHIP;
+    if ((rc = run_gather(s->ctx, a, false, st))) return rc;
     if (hipEventRecord(q->done, st) != hipSuccess) return VPLG_EHIP;
     return VPLG_OK;
 }

@@ -173,7 +173,11 @@ struct GenBuffers {
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
-hipError_t launch_gather(const GatherArgs& a, bool counted, hipStream_t s);
+// Persistent single-view gather: resets `counter` (a device word private to
+// stream `s`) and launches `blocks` workgroups that claim tiles from it.
+hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counter, int blocks, hipStream_t s);
+// Resident workgroups per CU of the single-view gather for `waves` waves per tile.
+hipError_t gather_occupancy(int waves, bool counted, int* blocks_per_cu);
 hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s);
 hipError_t launch_gather_batch(const BatchTable* tab, const GatherArgs* views, unsigned int* counter, int blocks,
                                hipStream_t s);
