@@ -261,7 +261,12 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
         std::memcpy(f, ints, sizeof f);
         o[3] = make_float4(f[0], f[1], f[2], f[3]);
     }
-    out_tris.resize(kTriStride * (size_t)T);
+    // three planes of T records: plane k holds each vertex permuted as
+    // (v[kx], v[ky], v[kz]) for dominant ray axis kz = k (kx, ky the next
+    // axes in cyclic order); plane 2 is the identity order and the only one
+    // with the normal
+    out_tris.assign(3 * kTriStride * (size_t)T, make_float4(0.f, 0.f, 0.f, 0.f));
+    float4* plane2 = out_tris.data() + 2 * kTriStride * (size_t)T;
     for (int i = 0; i < T; ++i) {
         int t = B.idx[i];
         const float* p = xyz + 9 * (size_t)t;
@@ -274,10 +279,17 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
         double cut = kParallelTau * kParallelTau *
                      ((double)nf[0] * nf[0] + (double)nf[1] * nf[1] + (double)nf[2] * nf[2]);
         if (!((float)cut > 0.f)) cut = HUGE_VAL;  // degenerate: never hit
-        out_tris[kTriStride * i] = make_float4(p[0], p[1], p[2], idf);
-        out_tris[kTriStride * i + 1] = make_float4(p[3], p[4], p[5], (float)cut);
-        out_tris[kTriStride * i + 2] = make_float4(p[6], p[7], p[8], 0.f);
-        out_tris[kTriStride * i + 3] = make_float4(nf[0], nf[1], nf[2], 0.f);
+        plane2[kTriStride * i] = make_float4(p[0], p[1], p[2], idf);
+        plane2[kTriStride * i + 1] = make_float4(p[3], p[4], p[5], (float)cut);
+        plane2[kTriStride * i + 2] = make_float4(p[6], p[7], p[8], 0.f);
+        plane2[kTriStride * i + 3] = make_float4(nf[0], nf[1], nf[2], 0.f);
+        for (int kz = 0; kz < 2; ++kz) {
+            const int kx = kz + 1, ky = (kz + 2) % 3;
+            float4* r = out_tris.data() + kTriStride * ((size_t)kz * T + i);
+            r[0] = make_float4(p[kx], p[ky], p[kz], idf);
+            r[1] = make_float4(p[3 + kx], p[3 + ky], p[3 + kz], (float)cut);
+            r[2] = make_float4(p[6 + kx], p[6 + ky], p[6 + kz], 0.f);
+        }
     }
     *n_leaves = B.n_leaves;
     *max_depth = B.max_depth;

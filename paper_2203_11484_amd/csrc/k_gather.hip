@@ -83,6 +83,10 @@ struct WtRay {
     float sx, sy, sz;
     float q;  // |d|^2 / d[kz]^2: scales the parallel-ray cut to the determinant
     int kx, ky, kz;
+    // pre: the records come from the scene's plane for this ray's kz (their
+    // vertices already permuted), and o[kx], o[ky], o[kz] are given
+    bool pre;
+    float okx, oky, okz;
 };
 
 __device__ __forceinline__ float sel3(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
@@ -100,6 +104,8 @@ __device__ __forceinline__ WtRay wt_ray(float ox, float oy, float oz, float dx, 
     r.sx = sel3(dx, dy, dz, r.kx) * r.sz;
     r.sy = sel3(dx, dy, dz, r.ky) * r.sz;
     r.q = fmaf(r.sy, r.sy, fmaf(r.sx, r.sx, 1.0f));
+    r.pre = false;
+    r.okx = r.oky = r.okz = 0.f;
     return r;
 }
 
@@ -123,14 +129,26 @@ __device__ __forceinline__ TriEval tri_eval(const Rec& rec, const WtRay& r)
     const float4 q0 = rec.q0, q1 = rec.q1, q2 = rec.q2;
     TriEval e;
     e.id = __float_as_int(q0.w);
-    // vertices relative to the ray origin, permuted and sheared into ray space
-    const float ax = q0.x - r.ox, ay = q0.y - r.oy, az = q0.z - r.oz;
-    const float bx = q1.x - r.ox, by = q1.y - r.oy, bz = q1.z - r.oz;
-    const float cx = q2.x - r.ox, cy = q2.y - r.oy, cz = q2.z - r.oz;
-    const float akz = sel3(ax, ay, az, r.kz), bkz = sel3(bx, by, bz, r.kz), ckz = sel3(cx, cy, cz, r.kz);
-    const float Ax = fmaf(-r.sx, akz, sel3(ax, ay, az, r.kx)), Ay = fmaf(-r.sy, akz, sel3(ax, ay, az, r.ky));
-    const float Bx = fmaf(-r.sx, bkz, sel3(bx, by, bz, r.kx)), By = fmaf(-r.sy, bkz, sel3(bx, by, bz, r.ky));
-    const float Cx = fmaf(-r.sx, ckz, sel3(cx, cy, cz, r.kx)), Cy = fmaf(-r.sy, ckz, sel3(cx, cy, cz, r.ky));
+    // vertices relative to the ray origin, permuted (a[kx], a[ky], a[kz]) ...
+    float akx, aky, akz, bkx, bky, bkz, ckx, cky, ckz;
+    if (r.pre) {
+        // ... by the record's plane already
+        akx = q0.x - r.okx, aky = q0.y - r.oky, akz = q0.z - r.okz;
+        bkx = q1.x - r.okx, bky = q1.y - r.oky, bkz = q1.z - r.okz;
+        ckx = q2.x - r.okx, cky = q2.y - r.oky, ckz = q2.z - r.okz;
+    } else {
+        // ... or per lane (the same differences, selected afterwards)
+        const float ax = q0.x - r.ox, ay = q0.y - r.oy, az = q0.z - r.oz;
+        const float bx = q1.x - r.ox, by = q1.y - r.oy, bz = q1.z - r.oz;
+        const float cx = q2.x - r.ox, cy = q2.y - r.oy, cz = q2.z - r.oz;
+        akx = sel3(ax, ay, az, r.kx), aky = sel3(ax, ay, az, r.ky), akz = sel3(ax, ay, az, r.kz);
+        bkx = sel3(bx, by, bz, r.kx), bky = sel3(bx, by, bz, r.ky), bkz = sel3(bx, by, bz, r.kz);
+        ckx = sel3(cx, cy, cz, r.kx), cky = sel3(cx, cy, cz, r.ky), ckz = sel3(cx, cy, cz, r.kz);
+    }
+    // ... and sheared into ray space
+    const float Ax = fmaf(-r.sx, akz, akx), Ay = fmaf(-r.sy, akz, aky);
+    const float Bx = fmaf(-r.sx, bkz, bkx), By = fmaf(-r.sy, bkz, bky);
+    const float Cx = fmaf(-r.sx, ckz, ckx), Cy = fmaf(-r.sy, ckz, cky);
     // edge functions: products rounded separately, so the two triangles of a
     // shared edge compute exact negatives of each other
     float U = Cx * By - Cy * Bx;
@@ -309,12 +327,22 @@ __device__ __forceinline__ bool packet_visible(const DevScene& sc, float ox, flo
     r.ox = ox * r.ix;
     r.oy = oy * r.iy;
     r.oz = oz * r.iz;
-    const WtRay wr = wt_ray(ox, oy, oz, dx, dy, dz);
+    WtRay wr = wt_ray(ox, oy, oz, dx, dy, dz);
     const float4* __restrict__ nodes = sc.nodes;
     const float4* __restrict__ tris = sc.tris;
     ex1 = __builtin_amdgcn_readfirstlane(ex1);  // uniform by contract; keeps the leaf loop scalar
-    // one sign pattern for every active lane: the slab entry planes are fixed
     const unsigned long long am = ballot(act);
+    // one dominant axis for every active lane: triangle records from that
+    // axis's plane, whose vertices need no per-lane permutation
+    const int kz0 = __builtin_amdgcn_readlane(wr.kz, __builtin_ctzll(am | (1ull << 63)));
+    if ((ballot(wr.kz != kz0) & am) == 0) {
+        wr.pre = true;
+        wr.okx = sel3(ox, oy, oz, wr.kx);
+        wr.oky = sel3(ox, oy, oz, wr.ky);
+        wr.okz = sel3(ox, oy, oz, wr.kz);
+        tris = sc.tris_rot + (size_t)kz0 * kTriStride * sc.n_tris;
+    }
+    // one sign pattern for every active lane: the slab entry planes are fixed
     const unsigned long long sx = ballot(r.ix < 0.f) & am, sy = ballot(r.iy < 0.f) & am, sz = ballot(r.iz < 0.f) & am;
     const bool uni = (sx == 0 || sx == am) && (sy == 0 || sy == am) && (sz == 0 || sz == am);
     const int oct = uni ? (sx ? 1 : 0) | (sy ? 2 : 0) | (sz ? 4 : 0) : 8;

@@ -306,7 +306,8 @@ int vplg_scene_upload(vplg_context* ctx, const float* tri_xyz, const float* tri_
     d.n_tris = n_tris;
     d.n_nodes = (int)(nodes.size() / 4);
     d.nodes = dn;
-    d.tris = dt;
+    d.tris_rot = dt;
+    d.tris = dt + 2 * kTriStride * (size_t)n_tris;
     d.xyz = dxyz;
     d.albedo = dalb;
     d.flags = dfl;

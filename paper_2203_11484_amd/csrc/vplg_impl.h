@@ -42,7 +42,11 @@ struct DevScene {
     int n_tris = 0;
     int n_nodes = 0;
     const float4* nodes = nullptr;    // 4 per node
-    const float4* tris = nullptr;     // 3 per leaf-ordered triangle
+    const float4* tris = nullptr;     // kTriStride per leaf-ordered triangle (identity order)
+    // [3][n_tris] records: plane k has every vertex as (v[kx], v[ky], v[kz])
+    // for dominant ray axis kz = k, kx and ky the next axes in cyclic order;
+    // plane 2 is `tris`
+    const float4* tris_rot = nullptr;
     const float* xyz = nullptr;       // original [T][3][3] float32
     const float* albedo = nullptr;    // [T][3]
     const uint8_t* flags = nullptr;   // [T]
