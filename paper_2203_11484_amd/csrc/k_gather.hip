@@ -154,7 +154,7 @@ __device__ __forceinline__ TriEval tri_eval(const Rec& rec, const WtRay& r)
     float U = Cx * By - Cy * Bx;
     float V = Ax * Cy - Ay * Cx;
     float W = Bx * Ay - By * Ax;
-    if (U == 0.f || V == 0.f || W == 0.f) {
+    if (fminf(fminf(fabsf(U), fabsf(V)), fabsf(W)) == 0.f) {
         // exact sign on an edge: float products are exact in double
         U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
         V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
@@ -164,9 +164,10 @@ __device__ __forceinline__ TriEval tri_eval(const Rec& rec, const WtRay& r)
     e.V = V;
     e.W = W;
     e.det = U + V + W;
-    const float T = fmaf(W, r.sz * ckz, fmaf(V, r.sz * bkz, U * (r.sz * akz)));
+    // t = T / det with T = sz (U a_kz + V b_kz + W c_kz)
+    const float T = fmaf(W, ckz, fmaf(V, bkz, U * akz));
     e.inv = rcpf(e.det);
-    e.t = T * e.inv;
+    e.t = T * (r.sz * e.inv);
     e.steep = e.det * e.det > q1.w * r.q;
     return e;
 }
