@@ -16,6 +16,8 @@
  *   G-buffer     closest hit of one primary ray per pixel centre
  *   gather       eq. (1) without the direct term: per pixel, the sum over all
  *                VPLs of (albedo/pi) * I_k * min(C, cos_p cos_k / r^2) * V
+ *   direct       the direct term L_e(y) of eq. (1) with the light model of
+ *                eq. (2)
  *   generation   Section "Close-Range VPL Sampling": near/far split of the
  *                one-sided faces, Morton-sorted area CDF cut into K strata,
  *                eq. (2) for the patch VPLs, and a sparse quasi-random walk
@@ -616,6 +618,73 @@ static olight make_light(const double* l)
         L.lc = L.pos;
     }
     return L;
+}
+
+/* ------------------------------------------------------------------------ */
+/* direct term L_e(y) of eq. (1)                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Sample points of the light, as eq. (2) uses them: the point light itself,
+ * or the 16 cell centres pos + eu (i + 1/2)/4 + ev (j + 1/2)/4 (cell j*4+i)
+ * of the quad.  Returns the count (1 or 16); xyz gets 3 doubles each. */
+int oracle_light_samples(const double* light, double* xyz)
+{
+    olight L = make_light(light);
+    if (L.kind == 0) {
+        xyz[0] = L.pos.x; xyz[1] = L.pos.y; xyz[2] = L.pos.z;
+        return 1;
+    }
+    for (int j = 0; j < 16; j++) {
+        v3 lj = vadd(vadd(L.pos, vscl(L.eu, ((double)(j % 4) + 0.5) / 4.0)), vscl(L.ev, ((double)(j / 4) + 0.5) / 4.0));
+        xyz[3 * j] = lj.x; xyz[3 * j + 1] = lj.y; xyz[3 * j + 2] = lj.z;
+    }
+    return 16;
+}
+
+/* Direct illumination L_e(y) of eq. (1) at each of n_px G-buffer entries:
+ * (albedo / pi) * Phi * g(x, n) with the light model of eq. (2): for the
+ * point light g = max(0, n.w) / (4 pi r^3), w = pos - x; for the quad,
+ * g = (1/16) sum_j max(0, n.w_j) max(0, -n_l.w_j) / (pi r_j^4) over the cell
+ * centres y_j, w_j = y_j - x.  Each sample counts only if V(x, y_j) = 1
+ * (host triangle excluded, the light's own triangles not).  Optional
+ * overrides (sorted by pixel, then sample) replace V for listed pairs. */
+void oracle_direct(void* h, const float* gpos, const float* gnrm, const float* galb, const int32_t* gtri,
+                   int64_t n_px, const double* light, double eps, const int32_t* ov_px, const int32_t* ov_s,
+                   const uint8_t* ov_vis, int64_t n_ov, double* Lout)
+{
+    const oscene* s = (const oscene*)h;
+    olight L = make_light(light);
+    double ys[48];
+    int ns = oracle_light_samples(light, ys);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < n_px; p++) {
+        double g = 0.0;
+        int tp = gtri[p];
+        if (tp >= 0) {
+            v3 x = vld(gpos + 3 * p), np = vld(gnrm + 3 * p);
+            int64_t lo = 0, hi = n_ov;
+            while (lo < hi) { int64_t mid = (lo + hi) / 2; if (ov_px[mid] < p) lo = mid + 1; else hi = mid; }
+            int64_t oi = lo;
+            for (int j = 0; j < ns; j++) {
+                v3 y = vldd(ys + 3 * j);
+                v3 w = vsub(y, x);
+                double r2 = vdot(w, w);
+                double cx = vdot(np, w);
+                double cl = L.kind == 0 ? 1.0 : -vdot(L.nl, w);
+                while (oi < n_ov && ov_px[oi] == p && ov_s[oi] < j) oi++;
+                if (!(cx > 0.0 && cl > 0.0)) continue;
+                int vis;
+                if (oi < n_ov && ov_px[oi] == p && ov_s[oi] == j) vis = ov_vis[oi];
+                else vis = visible(s, x, tp, y, -1, eps);
+                if (!vis) continue;
+                if (L.kind == 0) g += cx / ((4.0 * OR_PI) * (r2 * sqrt(r2)));
+                else g += (cx * cl) / (OR_PI * (r2 * r2));
+            }
+            if (L.kind == 1) g = g / 16.0;
+        }
+        for (int c = 0; c < 3; c++)
+            Lout[3 * p + c] = tp >= 0 ? ((double)galb[3 * p + c] / OR_PI) * (L.power[c] * g) : 0.0;
+    }
 }
 
 static uint32_t morton30(int cx, int cy, int cz)

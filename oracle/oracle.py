@@ -48,6 +48,9 @@ def lib():
         L.oracle_gather.argtypes = [_p, _p, _p, _p, _p, C.c_int64, _p, _p, _p, _p, C.c_int, C.c_double,
                                     C.c_double, _p, _p, _p, C.c_int64, C.c_int, _p]
         L.oracle_vis_matrix.argtypes = [_p, _p, _p, C.c_int64, _p, _p, C.c_int, C.c_double, _p]
+        L.oracle_light_samples.argtypes = [_p, _p]
+        L.oracle_light_samples.restype = C.c_int
+        L.oracle_direct.argtypes = [_p, _p, _p, _p, _p, C.c_int64, _p, C.c_double, _p, _p, _p, C.c_int64, _p]
         L.oracle_halton.restype = C.c_double
         L.oracle_halton.argtypes = [C.c_int, C.c_int64]
         L.oracle_patch_count.restype = C.c_int64
@@ -89,6 +92,14 @@ def morton30(cx, cy, cz):
 
 def num_threads():
     return lib().oracle_num_threads()
+
+
+def light_samples(light):
+    """The light's sample points as eq. (2) uses them: [1, 3] or [16, 3] FP64."""
+    la = light_array(light)
+    out = np.zeros((16, 3), np.float64)
+    n = lib().oracle_light_samples(_ptr(la), _ptr(out))
+    return out[:n].copy()
 
 
 class Scene:
@@ -177,6 +188,27 @@ class Scene:
         lib().oracle_gather(self.h, _ptr(gpos), _ptr(gnrm), _ptr(galb), _ptr(gtri), n, _ptr(vpos), _ptr(vnrm),
                             _ptr(vI), _ptr(vtri), M, float(C), float(eps), _ptr(op), _ptr(ov), _ptr(ob), nov,
                             int(nthreads), _ptr(L))
+        return L
+
+    def direct(self, gpos, gnrm, galb, gtri, light, eps=1e-4, overrides=None):
+        """Direct term L_e of eq. (1) (light model of eq. (2)) per G-buffer entry, [n, 3] FP64;
+        overrides = (pixel, sample, visibility) replace V for listed pairs."""
+        gpos, gnrm, galb = (_f32(a).reshape(-1, 3) for a in (gpos, gnrm, galb))
+        gtri = _i32(gtri)
+        n = len(gpos)
+        if overrides is not None:
+            op, os_, ob = overrides
+            order = np.lexsort((os_, op))
+            op, os_, ob = _i32(np.asarray(op)[order]), _i32(np.asarray(os_)[order]), \
+                np.ascontiguousarray(np.asarray(ob)[order], np.uint8)
+            nov = len(op)
+        else:
+            op = os_ = ob = None
+            nov = 0
+        la = light_array(light)
+        L = np.zeros((n, 3), np.float64)
+        lib().oracle_direct(self.h, _ptr(gpos), _ptr(gnrm), _ptr(galb), _ptr(gtri), n, _ptr(la), float(eps),
+                            _ptr(op), _ptr(os_), _ptr(ob), nov, _ptr(L))
         return L
 
     def vis_matrix(self, gpos, gtri, vpos, vtri, eps=1e-4):
