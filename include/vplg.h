@@ -247,6 +247,23 @@ int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t v
                                 const int32_t* pixels, int32_t n_px, uint32_t* vis_bits,
                                 const vplg_gather_params* p, void* stream);
 
+/* Direct term L_e(y) of eq. (1), the direct illumination of each G-buffer
+ * point by the scene's light with the light model of eq. (2):
+ *   radiance[c][p] = (albedo_p[c] / pi) * power[c] * G_p,
+ *   point light: G_p = V(x_p, pos) max(0, n_p.w) / (4 pi |w|^3), w = pos - x_p;
+ *   quad light:  G_p = (1/16) sum over the 16 cell centres y_j =
+ *                pos + edge_u (i + 1/2)/4 + edge_v (j + 1/2)/4 of
+ *                V(x_p, y_j) max(0, n_p.w_j) max(0, -n_l.w_j) / (pi |w_j|^4),
+ *                w_j = y_j - x_p, n_l = unit(edge_u x edge_v), the emitting side.
+ * Shadow segments x + s w, s in (t_eps, 1 - t_eps), skip the pixel's own
+ * triangle; the light's triangles (if any) occlude like any other.  Pixels
+ * with tri < 0 get 0; emitters seen directly get no emission term.  The
+ * three caller-owned device planes are overwritten.  FP32 arithmetic, samples
+ * summed in order (deterministic).  EINVAL: null pointers, bad G-buffer,
+ * t_eps outside [0, 0.5).  ENOTFOUND: unknown scene. */
+int vplg_direct(vplg_context* ctx, uint64_t scene_id, const vplg_gbuffer* gb, float* const radiance[3], float t_eps,
+                void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched gather and tile autotuning                                       */
 /* ------------------------------------------------------------------------ */

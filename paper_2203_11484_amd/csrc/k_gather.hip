@@ -595,6 +595,51 @@ __global__ __launch_bounds__(BLOCK) void k_vis_dump(VisDumpArgs a)
     }
 }
 
+// Direct term L_e(y) of eq. (1) with the light model of eq. (2): per pixel
+// (albedo / pi) * Phi * G, G = sum over the light's samples y_j of the
+// unoccluded max(0, n.w) / (4 pi r^3) (point light) or max(0, n.w)
+// max(0, -n_l.w) / (16 pi r^4) (quad cells), w = y_j - x, r = |w|.  One wave
+// per 8 x 8 tile; the 64 shadow rays to one sample form one packet, samples
+// summed in order.
+__global__ __launch_bounds__(BLOCK) void k_direct(DirectArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int W = a.gb.width, H = a.gb.height;
+    const int tiles_x = (W + 7) >> 3, tiles = tiles_x * ((H + 7) >> 3);
+    const int tile = blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= tiles) return;  // the whole wave
+    const int px = (tile % tiles_x) * 8 + (lane & 7), py = (tile / tiles_x) * 8 + (lane >> 3);
+    const bool in = px < W && py < H;
+    const int p = py * W + px;
+    int tp = -1;
+    float x = 0, y = 0, z = 0, nx = 0, ny = 0, nz = 0;
+    if (in) {
+        tp = a.gb.tri[p];
+        x = a.gb.pos[0][p]; y = a.gb.pos[1][p]; z = a.gb.pos[2][p];
+        nx = a.gb.nrm[0][p]; ny = a.gb.nrm[1][p]; nz = a.gb.nrm[2][p];
+    }
+    const bool valid = in && tp >= 0;
+    const bool quad = a.light.kind != 0;
+    const float tlo = a.t_eps, thi = 1.0f - a.t_eps;
+    Counters cnt;
+    float G = 0.f;
+    for (int j = 0; j < a.light.n_samples; ++j) {
+        const float wx = a.light.samples[j][0] - x, wy = a.light.samples[j][1] - y, wz = a.light.samples[j][2] - z;
+        const float r2 = fmaf(wz, wz, fmaf(wy, wy, wx * wx));
+        const float cx = fmaf(nz, wz, fmaf(ny, wy, nx * wx));
+        const float cl = quad ? -fmaf(a.light.nl[2], wz, fmaf(a.light.nl[1], wy, a.light.nl[0] * wx)) : 1.0f;
+        const bool act = valid && cx > 0.f && cl > 0.f;
+        if (ballot(act) == 0) continue;
+        const float g = quad ? (cx * cl) * rcpf(r2 * r2) : cx * rcpf(r2 * sqrtf(r2));
+        const bool vis = packet_visible<false>(a.scene, x, y, z, wx, wy, wz, act, tlo, thi, tp, -1, lane, cnt);
+        if (vis) G += g;
+    }
+    G *= quad ? 1.0f / (16.0f * 3.14159265358979323846f) : 1.0f / (4.0f * 3.14159265358979323846f);
+    if (in) {
+        for (int c = 0; c < 3; ++c) a.out[c][p] = valid ? a.gb.alb[c][p] * kInvPi * (a.light.power[c] * G) : 0.f;
+    }
+}
+
 // Closest hit, t in (0, inf); ties go to the smaller original triangle index.
 __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
 {
@@ -745,6 +790,13 @@ hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s)
     if (a.n_px == 0 || a.words == 0) return hipSuccess;
     dim3 grid((unsigned)((a.n_px + BLOCK - 1) / BLOCK));
     hipLaunchKernelGGL(k_vis_dump, grid, dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct(const DirectArgs& a, hipStream_t s)
+{
+    const int tiles = ((a.gb.width + 7) / 8) * ((a.gb.height + 7) / 8);
+    hipLaunchKernelGGL(k_direct, dim3((tiles + BLOCK / 64 - 1) / (BLOCK / 64)), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

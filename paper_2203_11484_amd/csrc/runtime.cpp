@@ -319,6 +319,21 @@ int vplg_scene_upload(vplg_context* ctx, const float* tri_xyz, const float* tri_
         so->light.ev[k] = light->edge_v[k];
         so->light.power[k] = light->power[k];
     }
+    // the light's sample points in FP64 (the point, or the 16 cell centres)
+    {
+        const double P[3] = {light->pos[0], light->pos[1], light->pos[2]};
+        const double U[3] = {light->edge_u[0], light->edge_u[1], light->edge_u[2]};
+        const double V[3] = {light->edge_v[0], light->edge_v[1], light->edge_v[2]};
+        so->light.n_samples = light->kind == 0 ? 1 : 16;
+        for (int j = 0; j < so->light.n_samples; ++j) {
+            const double a = light->kind == 0 ? 0.0 : ((double)(j % 4) + 0.5) / 4.0;
+            const double b = light->kind == 0 ? 0.0 : ((double)(j / 4) + 0.5) / 4.0;
+            for (int k = 0; k < 3; ++k) so->light.samples[j][k] = (float)((P[k] + U[k] * a) + V[k] * b);
+        }
+        const double n[3] = {U[1] * V[2] - U[2] * V[1], U[2] * V[0] - U[0] * V[2], U[0] * V[1] - U[1] * V[0]};
+        const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int k = 0; k < 3; ++k) so->light.nl[k] = l > 0 ? (float)(n[k] / l) : 0.f;
+    }
     so->info.n_tris = n_tris;
     so->info.n_nodes = d.n_nodes;
     so->info.n_leaves = n_leaves;
@@ -863,6 +878,28 @@ int vplg_gather_counted(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id
     if (!counters) return fail(VPLG_EINVAL, "null counters");
     a.counters = (unsigned long long*)counters;
     return run_gather(ctx, a, true, (hipStream_t)stream);
+}
+
+int vplg_direct(vplg_context* ctx, uint64_t scene_id, const vplg_gbuffer* gb, float* const radiance[3], float t_eps,
+                void* stream)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (!radiance) return fail(VPLG_EINVAL, "null radiance");
+    for (int c = 0; c < 3; ++c)
+        if (!radiance[c]) return fail(VPLG_EINVAL, "null radiance plane");
+    if ((rc = check_gbuffer(gb))) return rc;
+    if (!(t_eps >= 0.f && t_eps < 0.5f)) return fail(VPLG_EINVAL, "bad t_eps %g", t_eps);
+    SceneObj* so = find_scene(ctx, scene_id);
+    if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
+    DirectArgs a;
+    a.scene = so->dev;
+    a.light = so->light;
+    a.gb = dev_gbuffer(gb);
+    for (int c = 0; c < 3; ++c) a.out[c] = radiance[c];
+    a.t_eps = t_eps;
+    HIPCHK(launch_direct(a, (hipStream_t)stream));
+    return VPLG_OK;
 }
 
 int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,

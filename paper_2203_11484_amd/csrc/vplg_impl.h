@@ -57,6 +57,13 @@ struct DevScene {
 struct DevLight {
     int kind;  // 0 point, 1 quad
     float pos[3], eu[3], ev[3], power[3];
+    // sample points of the light as eq. (2) uses them (computed in FP64 on the
+    // host, stored as float32): the point itself, or the 16 quad cell centres
+    // pos + eu (i + 1/2)/4 + ev (j + 1/2)/4 (sample j*4+i); nl = the quad's
+    // unit normal edge_u x edge_v (its emitting side)
+    int n_samples;
+    float samples[16][3];
+    float nl[3];
 };
 
 // VPL set in structure-of-arrays form; count on the device for generated sets.
@@ -110,6 +117,15 @@ struct VisDumpArgs {
     int n_px;
     int words;  // ceil(capacity / 32)
     uint32_t* bits;
+    float t_eps;
+};
+
+// Direct term L_e(y) of eq. (1) over a G-buffer.
+struct DirectArgs {
+    DevScene scene;
+    DevLight light;
+    DevGBuffer gb;
+    float* out[3];
     float t_eps;
 };
 
@@ -187,6 +203,7 @@ hipError_t launch_gather_batch(const BatchTable* tab, const GatherArgs* views, u
                                hipStream_t s);
 hipError_t gather_batch_occupancy(int* blocks_per_cu);
 hipError_t launch_gbuffer(const GBufferArgs& a, hipStream_t s);
+hipError_t launch_direct(const DirectArgs& a, hipStream_t s);
 hipError_t launch_pack_vpls(const DevVpls& v, hipStream_t s);
 
 hipError_t launch_patch_levels(const DevScene& sc, double h, int32_t* level, long long* counts, hipStream_t s);

@@ -118,6 +118,7 @@ _SIGS = {
                                       C.POINTER(GatherParams), _p, _p]),
     "vplg_gather_visibility_dump": (C.c_int, [_p, _u64, _u64, C.POINTER(GBufferStruct), _p, C.c_int32, _p,
                                               C.POINTER(GatherParams), _p]),
+    "vplg_direct": (C.c_int, [_p, _u64, C.POINTER(GBufferStruct), C.POINTER(_p), C.c_float, _p]),
     "vplg_gather_batch": (C.c_int, [_p, C.POINTER(View), C.c_int32, _p]),
     "vplg_autotune": (C.c_int, [_p, _u64, _u64, C.POINTER(GBufferStruct), C.POINTER(_p), C.POINTER(GatherParams), _p,
                                 C.POINTER(C.c_int32)]),
@@ -382,6 +383,12 @@ def vplset_release(ctx, vplset_id):
 def gather(ctx, scene_id, vplset_id, gb, radiance, params=None, stream=None):
     gp = params if isinstance(params, GatherParams) else make_gather_params(params)
     _check(lib().vplg_gather(ctx, scene_id, vplset_id, C.byref(gb.struct), radiance_planes(radiance), C.byref(gp),
+                             _stream(stream)))
+
+
+def direct(ctx, scene_id, gb, radiance, t_eps=1e-4, stream=None):
+    """Direct term L_e of eq. (1) into radiance (torch [3, H, W] float32 on the device)."""
+    _check(lib().vplg_direct(ctx, scene_id, C.byref(gb.struct), radiance_planes(radiance), float(t_eps),
                              _stream(stream)))
 
 

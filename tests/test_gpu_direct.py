@@ -1,0 +1,122 @@
+"""Parity of the direct term L_e(y) of eq. (1) (through the C ABI) with the FP64 oracle.
+
+Both sides read the oracle's G-buffer (rounded to float32).  Visibility of every (pixel, light
+sample) pair comes from the gather's own shadow-ray code through the visibility dump (a VPL set
+holding the light's float32 sample points); every disagreement with the oracle must be grazing
+and at most 1e-4 of the cast pairs, and the radiance must then match per channel within 1e-4
+relative, with the oracle re-evaluated on the GPU's bit for the disagreeing pairs.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as orc  # noqa: E402
+from paper_2203_11484_amd import scenes  # noqa: E402
+from tests import helpers as H  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vplg():
+    from paper_2203_11484_amd import vplg as v
+    v.lib()
+    return v
+
+
+@pytest.fixture(scope="module")
+def ctx(vplg):
+    c = vplg.context_create(0)
+    yield c
+    vplg.context_destroy(c)
+
+
+def _samples32(light):
+    """The light's sample points as the library stores them: FP64 (pos + u a) + v b, rounded to float32."""
+    P, U, V = (np.asarray(light[k], np.float64) for k in ("pos", "edge_u", "edge_v"))
+    if light["kind"] == 0:
+        return P[None, :].astype(np.float32)
+    out = []
+    for j in range(16):
+        a, b = ((j % 4) + 0.5) / 4.0, ((j // 4) + 0.5) / 4.0
+        out.append((P + U * a) + V * b)
+    return np.array(out).astype(np.float32)
+
+
+def _check_direct(vplg, ctx, sc, label, eps=1e-4):
+    cam, light = sc["camera"], sc["light"]
+    W, Hh = cam["width"], cam["height"]
+    S = orc.Scene.from_dict(sc)
+    gbo = {k: (v.astype(np.float32) if v.dtype == np.float64 else v) for k, v in S.gbuffer(cam).items()}
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], light)
+    gb = vplg.GBuffer.from_arrays(gbo["pos"], gbo["nrm"], gbo["alb"], gbo["tri"], W, Hh)
+    rad = torch.full((3, Hh, W), -1.0, dtype=torch.float32, device="cuda")
+    vplg.direct(ctx, sid, gb, rad, eps)
+    torch.cuda.synchronize()
+    L_gpu = rad.cpu().numpy().reshape(3, -1).T.astype(np.float64)
+    ys = _samples32(light)
+    assert np.allclose(ys, orc.light_samples(light), rtol=1e-6, atol=1e-6)
+    # visibility of every pair through the gather's shadow-ray code
+    ns = len(ys)
+    vid = vplg.vpls_upload(ctx, ys, np.zeros_like(ys), np.zeros_like(ys), np.full(ns, -1, np.int32))
+    P = W * Hh
+    pix = torch.arange(P, dtype=torch.int32, device="cuda")
+    bits = torch.zeros((P, 1), dtype=torch.int32, device="cuda")
+    vplg.gather_visibility_dump(ctx, sid, vid, gb, pix, bits, dict(g_clamp=10.0, t_eps=eps))
+    torch.cuda.synchronize()
+    b = bits.cpu().numpy().view(np.uint32)[:, 0]
+    vis_gpu = ((b[:, None] >> np.arange(ns, dtype=np.uint32)[None, :]) & 1).astype(np.uint8)
+    vis_ref = S.vis_matrix(gbo["pos"], gbo["tri"], ys, np.full(ns, -1, np.int32), eps=eps)
+    dis = np.nonzero(vis_gpu != vis_ref)
+    # pairs the direct term shades: receiver (and, for the quad, emitter) cosine above 1e-5
+    w = ys.astype(np.float64)[None, :, :] - gbo["pos"].astype(np.float64)[:, None, :]
+    wl = np.linalg.norm(w, axis=2)
+    cast = (np.einsum("pkc,pc->pk", w, gbo["nrm"].astype(np.float64)) / wl > 1e-5) & (gbo["tri"][:, None] >= 0)
+    if light["kind"] == 1:
+        nl = np.cross(np.asarray(light["edge_u"], np.float64), np.asarray(light["edge_v"], np.float64))
+        nl /= np.linalg.norm(nl)
+        cast &= -np.einsum("pkc,c->pk", w, nl) / wl > 1e-5
+    n_pairs, n_dis_cast = int(cast.sum()), int(cast[dis].sum())
+    print(f"{label}: {len(dis[0])} disagreements, {n_dis_cast} over {n_pairs} cast pairs")
+    if len(dis[0]):
+        xi, ki = dis
+        graz = S.grazing(gbo["pos"][xi], gbo["tri"][xi], ys[ki], np.full(len(ki), -1, np.int32), eps=eps,
+                         delta_rel=1e-5)
+        assert graz.all(), f"{label}: {(graz == 0).sum()} non-grazing visibility disagreements"
+    assert n_dis_cast <= 1e-4 * n_pairs + 0.5
+    ov = (dis[0].astype(np.int32), dis[1].astype(np.int32), vis_gpu[dis]) if len(dis[0]) else None
+    L_ref = S.direct(gbo["pos"], gbo["nrm"], gbo["alb"], gbo["tri"], light, eps=eps, overrides=ov)
+    ok = H.radiance_close(L_gpu, L_ref, rel=1e-4)
+    assert ok.all(), f"{label}: {(~ok).sum()} of {len(ok)} pixels outside 1e-4"
+    assert (L_ref > 0).mean() > 0.3
+    vplg.vplset_release(ctx, vid)
+    vplg.scene_release(ctx, sid)
+
+
+@pytest.mark.parametrize("size", [(128, 128), (100, 75)])
+def test_direct_cornell_quad_light(vplg, ctx, size):
+    """Cornell box with its quad light (16 cells), every pixel: the full 128^2 image and a ragged one."""
+    _check_direct(vplg, ctx, scenes.make_scene("cornell", width=size[0], height=size[1]), f"cornell {size}")
+
+
+def test_direct_room20k_point_light(vplg, ctx):
+    """20k-triangle room with its point light, every pixel of the 512^2 image."""
+    _check_direct(vplg, ctx, scenes.make_scene("room20k"), "room20k")
+
+
+def test_direct_room200k_point_light(vplg, ctx):
+    """202k-triangle room at 1920 x 1080, every pixel."""
+    _check_direct(vplg, ctx, scenes.make_scene("room200k"), "room200k")
+
+
+def test_direct_errors(vplg, ctx):
+    sc = scenes.make_scene("cornell", width=16, height=16)
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
+    gb = vplg.GBuffer(16, 16)
+    rad = torch.zeros((3, 16, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(vplg.VplgError):
+        vplg.direct(ctx, sid + 12345, gb, rad)
+    with pytest.raises(vplg.VplgError):
+        vplg.direct(ctx, sid, gb, rad, t_eps=0.7)
+    vplg.scene_release(ctx, sid)
