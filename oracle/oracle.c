@@ -744,7 +744,7 @@ enum {
 
 /*
  * Full VPL generation.  cam = eye, target, up, vfov_deg, W, H; light = kind,
- * pos, edge_u, edge_v, power; ip = k_near, n_far, max_bounces, max_paths;
+ * pos, edge_u, edge_v, power; ip = k_near, n_far, max_bounces, max_paths, walk_near;
  * dp = d_near, patch_h.
  *
  * Outputs (caller-allocated):
@@ -769,6 +769,7 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
     olight L = make_light(light);
     int K = (int)ip[0], n_far = (int)ip[1], maxb = (int)ip[2];
     int64_t max_paths = ip[3];
+    int walk_near = (int)ip[4]; /* 1: near hits after the first bounce are kept as walk VPLs */
     double dn = dp[0], ph = dp[1];
     for (int i = 0; i < ST_COUNT; i++) stats[i] = 0;
     /* eight Halton bases: start (2 or 4 dimensions) + 2 per scatter */
@@ -904,7 +905,10 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
      * patches become VPLs, hits on near patches are discarded and the walk
      * continues.  Path i uses Halton index i with bases taken in prime
      * order as needed.  Stops with the path that brings the far count to
-     * n_far_t; fluxes are then divided by the number of paths. */
+     * n_far_t; fluxes are then divided by the number of paths.  Variant
+     * walk_near = 1 (not the paper's reading): only first-bounce near hits,
+     * the light the patch VPLs stand for, are discarded; later near hits
+     * become walk VPLs and count toward n_far_t. */
     int base_far = nv;
     int64_t path = 0;
     int nfar = 0;
@@ -950,7 +954,7 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
             if (a + b > n - 1) a = n - 1 - b;
             int down = (a + b <= n - 2) && ((U - (double)a) + (V - (double)b) > 1.0);
             int64_t g = patch_off[t] + (int64_t)b * (2 * n - b) + 2 * a + down;
-            if (!(pflags[g] & 1)) {
+            if (!(pflags[g] & 1) || (walk_near && bnc >= 2)) {
                 if (nv >= cap) { free(level); free(kp); free(tri_of); return -1; }
                 vpl_pos[3 * nv] = y.x; vpl_pos[3 * nv + 1] = y.y; vpl_pos[3 * nv + 2] = y.z;
                 vpl_nrm[3 * nv] = s->n[t].x; vpl_nrm[3 * nv + 1] = s->n[t].y; vpl_nrm[3 * nv + 2] = s->n[t].z;

@@ -422,3 +422,63 @@ def test_room_generation_counts():
     area = 0.5 * np.linalg.norm(np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0]), axis=1).sum()
     near_area = st["Q"] * _unit(0.1)
     assert 0.08 < near_area / area < 0.2
+
+
+# ---------------------------------------------------------------------------
+# walk variant: near hits kept after the first bounce
+# ---------------------------------------------------------------------------
+
+def _walk_vpl_patch_flags(sc, g):
+    """For each VPL, by brute-force point-in-patch over its triangle's patches: whether some owning patch
+    is far, and whether every owning patch is near (a point on a patch edge has several owners)."""
+    off, pf = g["patch_off"], g["pflags"]
+    any_far = np.zeros(g["n"], bool)
+    all_near = np.zeros(g["n"], bool)
+    for i in range(g["n"]):
+        if g["bounce"][i] == 0:
+            continue
+        t = g["tri"][i]
+        n = int(round(math.sqrt(off[t + 1] - off[t])))
+        owners = [loc for loc in range(n * n)
+                  if _point_in_tri(_patch_vertices(sc["tri"][t], n, loc), g["pos"][i], tol=1e-12)]
+        assert owners, i
+        near = [bool(pf[off[t] + loc] & 1) for loc in owners]
+        any_far[i] = not all(near)
+        all_near[i] = all(near)
+    return any_far, all_near
+
+
+def test_walk_near_variant_reduces_to_plain_ir_without_near_region():
+    """With no near region (d_near = 0) the variant changes nothing: the same VPLs bit for bit."""
+    sc = scenes.make_scene("cornell", d_near=0.0)
+    S = orc.Scene.from_dict(sc)
+    g0 = S.generate(sc["camera"], sc["light"], sc["params"])
+    g1 = S.generate(sc["camera"], sc["light"], dict(sc["params"], walk_near=1))
+    for k in ("pos", "nrm", "I", "tri", "path", "bounce"):
+        assert np.array_equal(g0[k], g1[k]), k
+
+
+def test_walk_near_variant_keeps_later_near_hits():
+    """Variant walk_near = 1: first-bounce walk VPLs are all on far patches, near hits are discarded only at
+    the first bounce, some later-bounce VPLs lie on near patches, and every walk VPL still carries
+    Phi_L times the albedo product along its path over N_paths (the furnace identity)."""
+    sc = _closed_box_scene(0.625, n_far=300, k_near=64, d_near=1.2)
+    S = orc.Scene.from_dict(sc, use_bvh=False)
+    p1 = dict(sc["params"], walk_near=1)
+    g = S.generate(sc["camera"], sc["light"], p1)
+    g0 = S.generate(sc["camera"], sc["light"], sc["params"])
+    st, st0 = g["stats"], g0["stats"]
+    assert st["k_eff"] == st0["k_eff"] == 64
+    assert st["n_far"] == st["n_far_target"]
+    walk = g["bounce"] > 0
+    any_far, all_near = _walk_vpl_patch_flags(sc, g)
+    assert any_far[walk & (g["bounce"] == 1)].all()
+    assert all_near[walk & (g["bounce"] >= 2)].any()
+    # the paper's reading never keeps a near hit, and discards more
+    any_far0, _ = _walk_vpl_patch_flags(sc, g0)
+    assert any_far0[g0["bounce"] > 0].all()
+    assert st["near_discarded"] < st0["near_discarded"]
+    PL = np.array([3.0, 2.0, 1.0])
+    phi = g["I"][walk] * math.pi * st["n_paths"]
+    for i, b in enumerate(g["bounce"][walk]):
+        np.testing.assert_allclose(phi[i], PL * 0.625 ** b, rtol=1e-12)
