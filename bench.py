@@ -246,6 +246,42 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_quality(args):
+    """The paper's equal-sample study (Section "Results") on the library's GPU path: RMSE of the indirect
+    image against a dense instant-radiosity reference (262,144 VPLs), hybrid vs plain IR at 1,024 and
+    5,120 VPLs, on the cornell, room20k and room200k workloads."""
+    import torch
+
+    from paper_2203_11484_amd import quality, scenes, vplg
+
+    torch.cuda.init()
+    ctx = vplg.context_create(0)
+    names = args.scenes.split(",")
+    out_rows = []
+    ratios = []
+    t0 = time.perf_counter()
+    for name in names:
+        sc = scenes.make_scene(name)
+        r = quality.equal_sample_study(vplg, ctx, sc, counts=(1024, 5120), ref_vpls=args.ref_vpls)
+        print(f"bench: quality {name}: ref RMS {r['ref_rms']:.4g}, " +
+              ", ".join(f"M={x['vpls']}: hybrid {x['hybrid_rmse']:.4g} hybrid+walk_near "
+                        f"{x['hybrid_walk_near_rmse']:.4g} IR {x['ir_rmse']:.4g}" for x in r["rows"] + [r["converged"]]),
+              file=sys.stderr, flush=True)
+        out_rows.append(r)
+        ratios += [x["ratio_ir_over_hybrid"] for x in r["rows"]]
+    vplg.context_destroy(ctx)
+    gm = math.exp(sum(math.log(x) for x in ratios) / len(ratios))
+    out = {
+        "metric": "indirect-image RMSE of plain instant radiosity / hybrid, equal VPL count (geometric mean)",
+        "value": gm, "unit": "ratio", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": (time.perf_counter() - t0) * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "quality", "scenes": names, "reference_vpls": args.ref_vpls, "counts": [1024, 5120]},
+        "studies": out_rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +293,8 @@ def main():
     ap.add_argument("--tile-vpl", type=int, default=0, help="waves (VPL slices) per 8x8 pixel tile, 0 = default")
     ap.add_argument("--autotune", action="store_true", help="batch64: autotune tile_vpl per view-shape bucket")
     ap.add_argument("--requests", type=int, default=64, help="serve: requests after 8 warm-ups")
+    ap.add_argument("--scenes", default="cornell,room20k,room200k", help="quality: workloads of the study")
+    ap.add_argument("--ref-vpls", type=int, default=262144, help="quality: VPLs of the dense-IR reference")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -269,6 +307,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "quality":
+        return bench_quality(args)
 
     import numpy as np
     import torch

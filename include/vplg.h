@@ -141,10 +141,16 @@ int vplg_gbuffer_render(vplg_context* ctx, uint64_t scene_id, const vplg_camera*
  * max_paths  cap on walk paths (reaching it sets stats.flags bit 0)
  * d_near     distance threshold of the near region
  * patch_h    faces are refined into patches with edges <= patch_h
- * t_eps      shadow-ray segment trim, as in the gather                      */
+ * t_eps      shadow-ray segment trim, as in the gather
+ * walk_near  0: the paper's flow step (3), every walk hit on a near patch is
+ *            discarded; 1 (a variant, not the paper's reading): only
+ *            first-bounce near hits are discarded (the patch VPLs stand for
+ *            that light), later near hits become walk VPLs and count toward
+ *            n_far.  Any other value is EINVAL.                              */
 typedef struct {
     int32_t k_near, n_far, max_bounces, max_paths;
     double d_near, patch_h, t_eps;
+    int32_t walk_near;
 } vplg_gen_params;
 
 typedef struct {

@@ -10,7 +10,8 @@
 //   5. place the VPL with the square-root triangle formula at Halton
 //      (2, 3)(k + 1), brightness from eq. (2) with area f(N)/K
 //   6. sparse quasi-random walk from the light; hits on far patches become
-//      VPLs, hits on near patches are discarded, until n_far VPLs exist
+//      VPLs, hits on near patches are discarded (in the walk_near variant
+//      only at the first bounce), until n_far VPLs exist
 //
 // Integer outcomes (levels, flags, order, strata, hit triangles, path
 // counts) are decided in FP64 with a fixed operation order so that a plain
@@ -583,7 +584,7 @@ __global__ void k_walk(DevScene s, DevLight dl, GenParams p, GenBuffers b, long 
         if (a + bb > n - 1) a = n - 1 - bb;
         int down = (a + bb <= n - 2) && ((U - (double)a) + (V - (double)bb) > 1.0);
         long long g = b.patch_off[t] + (long long)bb * (2 * n - bb) + 2 * a + down;
-        if (!(b.pflags[g] & 1)) {
+        if (!(b.pflags[g] & 1) || (p.walk_near && bnc >= 2)) {
             int slot = i * 3 + cnt;
             b.w_pos[3 * slot] = y.x; b.w_pos[3 * slot + 1] = y.y; b.w_pos[3 * slot + 2] = y.z;
             for (int c = 0; c < 3; ++c) b.w_flux[3 * slot + c] = flux[c];

@@ -412,6 +412,7 @@ int check_gen_params(const vplg_gen_params* p)
     if (!(p->patch_h > 0.0) || !std::isfinite(p->patch_h)) return fail(VPLG_EINVAL, "patch_h must be > 0");
     if (!(p->d_near >= 0.0)) return fail(VPLG_EINVAL, "d_near must be >= 0");
     if (!(p->t_eps >= 0.0 && p->t_eps < 0.5)) return fail(VPLG_EINVAL, "t_eps must be in [0, 0.5)");
+    if (p->walk_near != 0 && p->walk_near != 1) return fail(VPLG_EINVAL, "walk_near must be 0 or 1");
     return VPLG_OK;
 }
 
@@ -544,7 +545,7 @@ int alloc_genset(vplg_context* ctx, SceneObj* so, uint64_t scene_id, PatchIndex*
 int launch_genset(SceneObj* so, VplSetObj* v, const vplg_camera* cam, const vplg_gen_params* p, hipStream_t s)
 {
     CamBasis cb = cam_basis(cam);
-    GenParams gp{p->k_near, p->n_far, p->max_bounces, p->max_paths, p->d_near, p->patch_h, p->t_eps};
+    GenParams gp{p->k_near, p->n_far, p->max_bounces, p->max_paths, p->d_near, p->patch_h, p->t_eps, p->walk_near};
     HIPCHK(launch_generate(so->dev, so->light, cb, gp, v->dev, v->gen, s));
     HIPCHK(launch_pack_vpls(v->dev, s));
     HIPCHK(hipEventRecord(v->done, s));

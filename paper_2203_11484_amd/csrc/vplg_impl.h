@@ -150,6 +150,7 @@ struct CamBasis {
 struct GenParams {
     int k_near, n_far, max_bounces, max_paths;
     double d_near, patch_h, t_eps;
+    int walk_near;  // 1: near hits after the first bounce become walk VPLs
 };
 
 // Device-side record of one generation (counts are int64).

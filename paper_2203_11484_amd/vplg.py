@@ -53,7 +53,7 @@ class GBufferStruct(C.Structure):
 
 class GenParams(C.Structure):
     _fields_ = [("k_near", C.c_int32), ("n_far", C.c_int32), ("max_bounces", C.c_int32), ("max_paths", C.c_int32),
-                ("d_near", C.c_double), ("patch_h", C.c_double), ("t_eps", C.c_double)]
+                ("d_near", C.c_double), ("patch_h", C.c_double), ("t_eps", C.c_double), ("walk_near", C.c_int32)]
 
 
 class GenStats(C.Structure):
@@ -202,6 +202,7 @@ def make_gen_params(p):
     g.k_near, g.n_far, g.max_bounces = int(p["k_near"]), int(p["n_far"]), int(p["max_bounces"])
     g.max_paths = int(p["max_paths"])
     g.d_near, g.patch_h, g.t_eps = float(p["d_near"]), float(p["patch_h"]), float(p["t_eps"])
+    g.walk_near = int(p.get("walk_near", 0))
     return g
 
 

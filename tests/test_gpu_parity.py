@@ -198,14 +198,17 @@ def test_gbuffer_parity(vplg, ctx):
         vplg.scene_release(ctx, sid)
 
 
-@pytest.mark.parametrize("name", ["cornell", "room20k", "room200k"])
-def test_generation_parity(vplg, ctx, name):
-    """Every integer output of the generation bit-exact at the workloads' full sizes."""
+@pytest.mark.parametrize("name,walk_near", [("cornell", 0), ("room20k", 0), ("room200k", 0), ("cornell", 1),
+                                             ("room20k", 1)])
+def test_generation_parity(vplg, ctx, name, walk_near):
+    """Every integer output of the generation bit-exact at the workloads' full sizes, for the paper's
+    walk and for the variant that keeps near hits after the first bounce."""
     sc = scenes.make_scene(name)
+    prm = dict(sc["params"], walk_near=walk_near)
     S = orc.Scene.from_dict(sc)
-    ref = S.generate(sc["camera"], sc["light"], sc["params"])
+    ref = S.generate(sc["camera"], sc["light"], prm)
     sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
-    vid = vplg.vpls_generate(ctx, sid, sc["camera"], sc["params"])
+    vid = vplg.vpls_generate(ctx, sid, sc["camera"], prm)
     st = vplg.vplset_stats(ctx, vid)
     rs = ref["stats"]
     for k_gpu, k_ref in (("n_patches", "n_patches"), ("n_near", "n_near"), ("n_eligible", "n_eligible"),
