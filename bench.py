@@ -119,8 +119,11 @@ def bench_batch(args):
     torch.cuda.synchronize()
     ref = [v["radiance"].clone() for v in views]
     ev[2].record(stream)
-    for v in views:  # the plain one-frame-per-launch gather of the same views
-        vplg.gather(ctx, v["scene"], v["vplset"], v["gb"], v["radiance"], v["params"], stream)
+    # the plain one-frame-per-launch gather of the same views, at the tile shape the batch resolved
+    # (untuned views: 8 waves per tile in a batch, the tile-count rule alone)
+    plain = [dict(v["params"], tile_vpl=0 if args.autotune else 8) for v in views]
+    for v, p in zip(views, plain):
+        vplg.gather(ctx, v["scene"], v["vplset"], v["gb"], v["radiance"], p, stream)
     ev[3].record(stream)
     torch.cuda.synchronize()
     same = all(torch.equal(a, v["radiance"]) for a, v in zip(ref, views))

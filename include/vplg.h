@@ -216,7 +216,9 @@ int vplg_vplset_release(vplg_context* ctx, uint64_t vplset_id);
 /* g_clamp: C in min(C, cos_p cos_k / r^2) (> 0).  t_eps: shadow segments
  * x + s (y - x) test s in (t_eps, 1 - t_eps), both host triangles excluded.
  * tile_px: pixels per tile, 0 or 64 (8 x 8).  tile_vpl: waves sharing one
- * tile, each taking every tile_vpl-th VPL: 0 (= 8) or 1, 2, 4, 8, 16. */
+ * tile, each taking every tile_vpl-th VPL: 1, 2, 4, 8 or 16, or 0: the
+ * autotuned choice for the view's shape, else 16 for a view of fewer than
+ * 32 tiles per compute unit (it shortens the launch's tail) and 8 above. */
 typedef struct {
     float g_clamp, t_eps;
     int32_t tile_px, tile_vpl;
@@ -276,7 +278,8 @@ int vplg_direct(vplg_context* ctx, uint64_t scene_id, const vplg_gbuffer* gb, fl
 
 /* One view of a batch: a resident scene and VPL set, its G-buffer, its
  * radiance planes and gather parameters (params.tile_vpl 0 = the autotuned
- * choice for the view's shape; a batch accepts 1, 2, 4 or 8). */
+ * choice for the view's shape, else 8: a batch shares one tail, so the
+ * tile-count rule of a lone gather does not apply). */
 typedef struct {
     uint64_t scene_id, vplset_id;
     vplg_gbuffer gb;
@@ -290,18 +293,21 @@ typedef struct {
  * HIP graph captured once per context and replayed; each call only rewrites
  * the device work table (copied from pinned host staging on `stream`) before
  * the replay.  Every view's radiance is identical to vplg_gather's with the
- * same tile_vpl, whatever else is in the batch.  Calls on one context must
+ * same resolved tile_vpl, whatever else is in the batch.  A batch that holds
+ * a 16-wave view runs in 16-wave workgroups (a second graph, captured on
+ * first use), else in 8-wave ones.  Calls on one context must
  * not overlap (they share the work table); the call waits only for the
  * previous call's table copy. */
 int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views, void* stream);
 
-/* Time vplg_gather with tile_vpl 1, 2, 4 and 8 on this view (synchronises
+/* Time vplg_gather with tile_vpl 1, 2, 4, 8 and 16 on this view (synchronises
  * `stream`), remember the fastest for the view's shape bucket
  * (ceil(log2(pixels)), ceil(log2(VPL capacity))) and return it.  Later
  * gathers with tile_vpl 0 in that bucket use it. */
 int vplg_autotune(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                   float* const radiance[3], const vplg_gather_params* p, void* stream, int32_t* best_tile_vpl);
-/* The tile_vpl a gather of this shape uses with tile_vpl 0 (8 if untuned). */
+/* The tile_vpl a gather of this shape uses with tile_vpl 0 (the tile-count
+ * rule of vplg_gather_params if untuned). */
 int vplg_autotune_lookup(vplg_context* ctx, int32_t width, int32_t height, int32_t n_vpls, int32_t* tile_vpl);
 /* Save / merge the autotuned table as text ("vplg-autotune 1", then lines
  * "log2_pixels log2_vpls tile_vpl").  load: ENOTFOUND if the file is absent. */

@@ -22,7 +22,6 @@ constexpr int BLOCK = 256;              // 4 wave64 per workgroup (G-buffer, dum
 constexpr int kGatherMaxWaves = 16;     // waves per gather workgroup (VPL slices of one tile)
 constexpr int kGatherMaxThreads = 64 * kGatherMaxWaves;
 constexpr int kChunk = 16;              // VPLs per first-level partial sum of a wave
-constexpr int kBatchWaves = kBatchBlockWaves;  // waves per persistent workgroup
 constexpr float kInvPi = 0.318309886183790671538f;
 
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -515,15 +514,15 @@ __global__ __launch_bounds__(kGatherMaxThreads) void k_gather_counted(GatherArgs
     gather_persistent<true>(a, counter);
 }
 
-// Persistent gather over many views.  Each workgroup of kBatchWaves waves
-// claims work items from a device counter until none is left (every
-// workgroup reaches the exit).  Item i of view v covers tiles
-// [j * g, (j + 1) * g) with g = kBatchWaves / w_v tile groups of w_v waves.
-__global__ __launch_bounds__(64 * kBatchWaves) __attribute__((amdgpu_waves_per_eu(8))) void k_gather_batch(const BatchTable* __restrict__ tab,
-                                                                    const GatherArgs* __restrict__ views,
-                                                                    unsigned int* __restrict__ counter)
+// Persistent gather over many views.  Each workgroup of BW waves claims
+// work items from a device counter until none is left (every workgroup
+// reaches the exit).  Item i of view v covers tiles [j * g, (j + 1) * g)
+// with g = BW / w_v tile groups of w_v waves.
+template <int BW>
+__global__ __launch_bounds__(64 * BW) __attribute__((amdgpu_waves_per_eu(8))) void k_gather_batch(
+    const BatchTable* __restrict__ tab, const GatherArgs* __restrict__ views, unsigned int* __restrict__ counter)
 {
-    __shared__ float s_red[kBatchWaves][3][64];
+    __shared__ float s_red[BW][3][64];
     __shared__ int s_item;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -544,7 +543,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) __attribute__((amdgpu_waves_per_e
         }
         const GatherArgs& a = views[lo];
         const int w = tab->waves[lo];
-        const int groups = kBatchWaves / w;
+        const int groups = BW / w;
         const int group = wave / w;
         const int tiles = ((a.gb.width + 7) >> 3) * ((a.gb.height + 7) >> 3);
         const int tile = (item - tab->prefix[lo]) * groups + group;
@@ -773,16 +772,26 @@ hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counte
 }
 
 hipError_t launch_gather_batch(const BatchTable* tab, const GatherArgs* views, unsigned int* counter, int blocks,
-                               hipStream_t s)
+                               int block_waves, hipStream_t s)
 {
+    if (block_waves != kBatchBlockWaves && block_waves != kBatchWideWaves) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-    hipLaunchKernelGGL(k_gather_batch, dim3(blocks), dim3(64 * kBatchWaves), 0, s, tab, views, counter);
+    if (block_waves == kBatchWideWaves)
+        hipLaunchKernelGGL(k_gather_batch<kBatchWideWaves>, dim3(blocks), dim3(64 * kBatchWideWaves), 0, s, tab, views,
+                           counter);
+    else
+        hipLaunchKernelGGL(k_gather_batch<kBatchBlockWaves>, dim3(blocks), dim3(64 * kBatchBlockWaves), 0, s, tab,
+                           views, counter);
     return hipGetLastError();
 }
 
-hipError_t gather_batch_occupancy(int* blocks_per_cu)
+hipError_t gather_batch_occupancy(int block_waves, int* blocks_per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gather_batch, 64 * kBatchWaves, 0);
+    if (block_waves == kBatchWideWaves)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gather_batch<kBatchWideWaves>,
+                                                            64 * kBatchWideWaves, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_gather_batch<kBatchBlockWaves>,
+                                                        64 * kBatchBlockWaves, 0);
 }
 
 hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s)

@@ -211,8 +211,10 @@ int vplg_context_destroy(vplg_context* ctx)
         delete kv.second;
     }
     BatchEngine& be = ctx->batch;
-    if (be.exec) (void)hipGraphExecDestroy(be.exec);
-    if (be.graph) (void)hipGraphDestroy(be.graph);
+    for (int i = 0; i < 2; ++i) {
+        if (be.exec[i]) (void)hipGraphExecDestroy(be.exec[i]);
+        if (be.graph[i]) (void)hipGraphDestroy(be.graph[i]);
+    }
     if (be.capture) (void)hipStreamDestroy(be.capture);
     if (be.staged) (void)hipEventDestroy(be.staged);
     if (be.d_tab) (void)hipFree(be.d_tab);
@@ -787,14 +789,19 @@ static uint32_t shape_bucket(int width, int height, int n_vpls)
     return (ceil_log2((long long)width * height) << 8) | ceil_log2(n_vpls > 0 ? n_vpls : 1);
 }
 
-int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls)
+int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls, bool batched)
 {
     auto it = ctx->tuned.find(shape_bucket(width, height, n_vpls));
-    return it == ctx->tuned.end() ? 8 : it->second;
+    if (it != ctx->tuned.end()) return it->second;
+    if (batched) return 8;
+    if (ctx->cus == 0 && hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
+        ctx->cus = 256;
+    const long long tiles = (long long)((width + 7) / 8) * ((height + 7) / 8);
+    return tiles < (long long)kWideTilesPerCu * ctx->cus ? 16 : 8;
 }
 
 int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
-                         float* const radiance[3], const vplg_gather_params* p, GatherArgs* a)
+                  float* const radiance[3], const vplg_gather_params* p, GatherArgs* a, bool batched)
 {
     int rc = set_device(ctx);
     if (rc) return rc;
@@ -808,11 +815,11 @@ int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, cons
     if (!so) return fail(VPLG_ENOTFOUND, "unknown scene %llu", (unsigned long long)scene_id);
     VplSetObj* v = find_set(ctx, vplset_id);
     if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
-    return gather_args(ctx, so, v, gb, radiance, p, a);
+    return gather_args(ctx, so, v, gb, radiance, p, a, batched);
 }
 
 int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffer* gb, float* const radiance[3],
-                const vplg_gather_params* p, GatherArgs* a)
+                const vplg_gather_params* p, GatherArgs* a, bool batched)
 {
     a->scene = so->dev;
     a->vpls = v->dev;
@@ -821,8 +828,8 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
     a->g_clamp = p->g_clamp;
     a->t_eps = p->t_eps;
     a->counters = nullptr;
-    // tile_vpl: waves (VPL slices) per 8 x 8 tile; 0 = the autotuned choice for this view shape, else 8
-    int w = p->tile_vpl == 0 ? tuned_waves(ctx, gb->width, gb->height, v->dev.capacity) : p->tile_vpl;
+    // tile_vpl: waves (VPL slices) per 8 x 8 tile; 0 = the autotuned choice, else the tile-count rule
+    int w = p->tile_vpl == 0 ? tuned_waves(ctx, gb->width, gb->height, v->dev.capacity, batched) : p->tile_vpl;
     if (w < 1 || w > 16 || (w & (w - 1)))
         return fail(VPLG_EINVAL, "tile_vpl must be 0 or a power of two in [1, 16] (got %d)", p->tile_vpl);
     if (p->tile_px != 0 && p->tile_px != 64) return fail(VPLG_EINVAL, "tile_px must be 0 or 64 (8 x 8 pixels)");
@@ -932,29 +939,32 @@ int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t v
 
 }  // extern "C"
 
-static int batch_init(vplg_context* ctx)
+static int batch_init(vplg_context* ctx, int wide)
 {
     BatchEngine& be = ctx->batch;
-    if (be.ready) return VPLG_OK;
-    HIPCHK(hipMalloc(&be.d_tab, sizeof(BatchTable)));
-    HIPCHK(hipMalloc(&be.d_views, sizeof(GatherArgs) * kBatchMaxViews));
-    HIPCHK(hipMalloc(&be.d_counter, sizeof(unsigned int)));
-    HIPCHK(hipHostMalloc(&be.h_tab, sizeof(BatchTable), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc(&be.h_views, sizeof(GatherArgs) * kBatchMaxViews, hipHostMallocDefault));
-    HIPCHK(hipEventCreateWithFlags(&be.staged, hipEventDisableTiming));
-    HIPCHK(hipStreamCreateWithFlags(&be.capture, hipStreamNonBlocking));
+    if (!be.ready) {
+        HIPCHK(hipMalloc(&be.d_tab, sizeof(BatchTable)));
+        HIPCHK(hipMalloc(&be.d_views, sizeof(GatherArgs) * kBatchMaxViews));
+        HIPCHK(hipMalloc(&be.d_counter, sizeof(unsigned int)));
+        HIPCHK(hipHostMalloc(&be.h_tab, sizeof(BatchTable), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(&be.h_views, sizeof(GatherArgs) * kBatchMaxViews, hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&be.staged, hipEventDisableTiming));
+        HIPCHK(hipStreamCreateWithFlags(&be.capture, hipStreamNonBlocking));
+        be.ready = true;
+    }
+    if (be.exec[wide]) return VPLG_OK;
+    const int bw = wide ? kBatchWideWaves : kBatchBlockWaves;
     int cus = 0, per_cu = 0;
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    HIPCHK(gather_batch_occupancy(&per_cu));
-    be.blocks = cus * (per_cu > 0 ? per_cu : 1);
+    HIPCHK(gather_batch_occupancy(bw, &per_cu));
+    be.blocks[wide] = cus * (per_cu > 0 ? per_cu : 1);
     // the graph holds only fixed device pointers: the table's contents change between replays
     HIPCHK(hipStreamBeginCapture(be.capture, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_gather_batch(be.d_tab, be.d_views, be.d_counter, be.blocks, be.capture);
-    hipError_t e2 = hipStreamEndCapture(be.capture, &be.graph);
+    hipError_t e = launch_gather_batch(be.d_tab, be.d_views, be.d_counter, be.blocks[wide], bw, be.capture);
+    hipError_t e2 = hipStreamEndCapture(be.capture, &be.graph[wide]);
     if (e != hipSuccess) return fail(VPLG_EHIP, "batch capture: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(VPLG_EHIP, "batch capture end: %s", hipGetErrorString(e2));
-    HIPCHK(hipGraphInstantiate(&be.exec, be.graph, nullptr, nullptr, 0));
-    be.ready = true;
+    HIPCHK(hipGraphInstantiate(&be.exec[wide], be.graph[wide], nullptr, nullptr, 0));
     return VPLG_OK;
 }
 
@@ -971,20 +981,23 @@ int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views
     std::vector<GatherArgs> args(n_views);
     std::vector<int> waves(n_views), items(n_views);
     std::vector<double> cost(n_views);
+    int wide = 0;
     for (int v = 0; v < n_views; ++v) {
         const vplg_view& vw = views[v];
-        if ((rc = gather_common(ctx, vw.scene_id, vw.vplset_id, &vw.gb, vw.radiance, &vw.params, &args[v])))
+        if ((rc = gather_common(ctx, vw.scene_id, vw.vplset_id, &vw.gb, vw.radiance, &vw.params, &args[v], true)))
             return fail(rc, "view %d: %s", v, g_err.c_str());
-        if (args[v].waves_per_tile > kBatchBlockWaves)
-            return fail(VPLG_EINVAL, "view %d: tile_vpl %d exceeds %d in a batch", v, args[v].waves_per_tile,
-                        kBatchBlockWaves);
         waves[v] = args[v].waves_per_tile;
-        const int tiles = ((vw.gb.width + 7) / 8) * ((vw.gb.height + 7) / 8);
-        const int groups = kBatchBlockWaves / waves[v];
-        items[v] = (tiles + groups - 1) / groups;
+        if (waves[v] > kBatchBlockWaves) wide = 1;
         cost[v] = (double)vw.gb.width * vw.gb.height * (double)args[v].vpls.capacity;
     }
-    if ((rc = batch_init(ctx))) return rc;
+    // one workgroup size per launch: 16 waves when some view runs 16 per tile
+    const int bw = wide ? kBatchWideWaves : kBatchBlockWaves;
+    for (int v = 0; v < n_views; ++v) {
+        const int tiles = ((views[v].gb.width + 7) / 8) * ((views[v].gb.height + 7) / 8);
+        const int groups = bw / waves[v];
+        items[v] = (tiles + groups - 1) / groups;
+    }
+    if ((rc = batch_init(ctx, wide))) return rc;
     BatchEngine& be = ctx->batch;
     // most expensive views first (their tiles are claimed first), ties by index
     std::vector<int> order(n_views);
@@ -1006,7 +1019,7 @@ int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views
     HIPCHK(hipMemcpyAsync(be.d_tab, be.h_tab, sizeof(BatchTable), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(be.d_views, be.h_views, sizeof(GatherArgs) * n_views, hipMemcpyHostToDevice, s));
     HIPCHK(hipEventRecord(be.staged, s));
-    HIPCHK(hipGraphLaunch(be.exec, s));
+    HIPCHK(hipGraphLaunch(be.exec[wide], s));
     return VPLG_OK;
 }
 
@@ -1021,7 +1034,7 @@ int vplg_autotune(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, cons
     float best_ms = 1e30f;
     int best = 8;
     int n_vpls = 0;
-    for (int w = 1; w <= kBatchBlockWaves; w <<= 1) {
+    for (int w = 1; w <= kBatchWideWaves; w <<= 1) {
         vplg_gather_params q = *p;
         q.tile_vpl = w;
         GatherArgs a;
@@ -1060,7 +1073,7 @@ int vplg_autotune(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, cons
 int vplg_autotune_lookup(vplg_context* ctx, int32_t width, int32_t height, int32_t n_vpls, int32_t* tile_vpl)
 {
     if (!ctx || !tile_vpl) return fail(VPLG_EINVAL, "null argument");
-    *tile_vpl = tuned_waves(ctx, width, height, n_vpls);
+    *tile_vpl = tuned_waves(ctx, width, height, n_vpls, false);
     return VPLG_OK;
 }
 
@@ -1089,7 +1102,7 @@ int vplg_autotune_load(vplg_context* ctx, const char* path)
     int w;
     std::map<uint32_t, int> t;
     while (std::fscanf(f, "%u %u %d", &px, &nv, &w) == 3) {
-        if (px > 63 || nv > 255 || w < 1 || w > kBatchBlockWaves || (w & (w - 1))) {
+        if (px > 63 || nv > 255 || w < 1 || w > kBatchWideWaves || (w & (w - 1))) {
             std::fclose(f);
             return fail(VPLG_EINVAL, "bad autotune entry in %s", path);
         }

@@ -72,9 +72,10 @@ struct BatchEngine {
     GatherArgs* h_views = nullptr;
     hipEvent_t staged = nullptr;  // last use of the pinned staging
     hipStream_t capture = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int blocks = 0;
+    // [0]: workgroups of 8 waves, [1]: of 16 waves (captured on first use)
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int blocks[2] = {0, 0};
     bool ready = false;
 };
 
@@ -131,11 +132,17 @@ uint64_t genset_bytes(long long n_patches, int k_near, int n_far);
 int alloc_genset(vplg_context* ctx, SceneObj* so, uint64_t scene_id, PatchIndex* pi, const vplg_gen_params* p,
                  VplSetObj** out);
 int launch_genset(SceneObj* so, VplSetObj* v, const vplg_camera* cam, const vplg_gen_params* p, hipStream_t s);
-int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls);
+constexpr int kWideTilesPerCu = 32;
+// waves per 8 x 8 tile for a view: the autotuned choice for its shape, else,
+// for a view launched alone, 16 when it has fewer than kWideTilesPerCu tiles
+// per CU (shorter work items shorten the launch's tail) and 8 above; a view in
+// a batch gets 8 (the batch shares one tail, and 16-wave workgroups would tie
+// the 8-wave views' tile pairs to common barriers)
+int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls, bool batched);
 int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
-                  float* const radiance[3], const vplg_gather_params* p, GatherArgs* a);
+                  float* const radiance[3], const vplg_gather_params* p, GatherArgs* a, bool batched = false);
 int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffer* gb, float* const radiance[3],
-                const vplg_gather_params* p, GatherArgs* a);
+                const vplg_gather_params* p, GatherArgs* a, bool batched = false);
 // launch the persistent single-view gather of `a` on `s` (its stream's tile counter, resident grid)
 int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s);
 

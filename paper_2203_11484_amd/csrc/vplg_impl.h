@@ -100,7 +100,8 @@ struct GatherArgs {
 // Work table of a batched gather: views sorted by the caller, prefix[v] =
 // first work item of view v (prefix[n_views] = total), waves[v] = waves per
 // tile of view v (1, 2, 4 or 8).
-constexpr int kBatchBlockWaves = 8;
+constexpr int kBatchBlockWaves = 8;   // waves per persistent batch workgroup (views of <= 8 waves per tile)
+constexpr int kBatchWideWaves = 16;   // the wide variant, used when a batch holds a 16-wave view
 constexpr int kBatchMaxViews = 4096;
 struct BatchTable {
     int n_views;
@@ -201,8 +202,8 @@ hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counte
 hipError_t gather_occupancy(int waves, bool counted, int* blocks_per_cu);
 hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s);
 hipError_t launch_gather_batch(const BatchTable* tab, const GatherArgs* views, unsigned int* counter, int blocks,
-                               hipStream_t s);
-hipError_t gather_batch_occupancy(int* blocks_per_cu);
+                               int block_waves, hipStream_t s);
+hipError_t gather_batch_occupancy(int block_waves, int* blocks_per_cu);
 hipError_t launch_gbuffer(const GBufferArgs& a, hipStream_t s);
 hipError_t launch_direct(const DirectArgs& a, hipStream_t s);
 hipError_t launch_pack_vpls(const DevVpls& v, hipStream_t s);

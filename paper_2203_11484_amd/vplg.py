@@ -211,6 +211,8 @@ def make_gather_params(p=None, g_clamp=10.0, t_eps=1e-4):
         g_clamp, t_eps = p.get("g_clamp", g_clamp), p.get("t_eps", t_eps)
     g = GatherParams()
     g.g_clamp, g.t_eps, g.tile_px, g.tile_vpl = float(g_clamp), float(t_eps), 0, 0
+    if p is not None:
+        g.tile_px, g.tile_vpl = int(p.get("tile_px", 0)), int(p.get("tile_vpl", 0))
     return g
 
 

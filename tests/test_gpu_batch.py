@@ -28,14 +28,15 @@ def ctx(vplg):
 
 
 def _views(vplg, ctx):
-    """Six views over two scenes: ragged sizes, different VPL budgets and tile shapes."""
+    """Seven views over two scenes: ragged sizes, different VPL budgets and tile shapes (1 to 16 waves per
+    tile, so the batch runs in 16-wave workgroups; a subset without a 16-wave view runs in 8-wave ones)."""
     sc_a = scenes.make_scene("cornell")
     sc_b = scenes.procedural_room(11, 6, 6, 2, 2, k_near=192, n_far=320, d_near=7.0)
     ids = {}
     for key, sc in (("a", sc_a), ("b", sc_b)):
         ids[key] = (sc, vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"]))
     specs = [("a", 40, 36, 1), ("b", 64, 64, 8), ("a", 100, 75, 4), ("b", 72, 40, 2), ("b", 33, 17, 8),
-             ("a", 128, 96, 0)]
+             ("a", 128, 96, 0), ("b", 56, 48, 16)]
     views = []
     for key, w, h, tv in specs:
         sc, sid = ids[key]
@@ -55,8 +56,11 @@ def test_batch_equals_per_view_and_replays(vplg, ctx):
     views = _views(vplg, ctx)
     refs = []
     for v in views:
+        # tile_vpl 0 resolves to 8 in a batch (untuned); a lone gather's rule would pick 16 for these sizes
+        gp = vplg.make_gather_params(v["sc"]["params"])
+        gp.tile_vpl = v["params"].tile_vpl or 8
         r = torch.zeros_like(v["radiance"])
-        vplg.gather(ctx, v["scene"], v["vplset"], v["gb"], r, v["params"])
+        vplg.gather(ctx, v["scene"], v["vplset"], v["gb"], r, gp)
         refs.append(r)
     torch.cuda.synchronize()
     for rep in range(3):
@@ -77,6 +81,25 @@ def test_batch_equals_per_view_and_replays(vplg, ctx):
     for v in sub:
         i = views.index(v)
         assert torch.equal(v["radiance"], refs[i])
+
+
+def test_untuned_tile_vpl_rule(vplg, ctx):
+    """tile_vpl 0 on an untuned shape: a lone gather takes 16 waves per tile below 32 tiles per compute
+    unit (bit for bit the explicit 16), a view in a batch takes 8."""
+    v = _views(vplg, ctx)[5]
+    assert v["params"].tile_vpl == 0
+    out = {}
+    for tv in (0, 8, 16):
+        gp = vplg.make_gather_params(v["sc"]["params"])
+        gp.tile_vpl = tv
+        out[tv] = torch.zeros_like(v["radiance"])
+        vplg.gather(ctx, v["scene"], v["vplset"], v["gb"], out[tv], gp)
+    v["radiance"].fill_(-1.0)
+    vplg.gather_batch(ctx, [v])
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], out[16])
+    assert torch.equal(v["radiance"], out[8])
+    assert torch.allclose(out[8], out[16], rtol=1e-5, atol=1e-7)
 
 
 def test_batch_view_matches_oracle(vplg, ctx):
@@ -108,7 +131,7 @@ def test_batch_rejects_bad_views(vplg, ctx):
         vplg.gather_batch(ctx, [views[0], bad])
     assert e.value.code == vplg.ENOTFOUND
     gp = vplg.make_gather_params()
-    gp.tile_vpl = 16
+    gp.tile_vpl = 3
     big = dict(views[0])
     big["params"] = gp
     with pytest.raises(vplg.VplgError) as e:
@@ -119,14 +142,18 @@ def test_batch_rejects_bad_views(vplg, ctx):
 def test_autotune_roundtrip(vplg, ctx, tmp_path):
     v = _views(vplg, ctx)[1]
     best = vplg.autotune(ctx, v["scene"], v["vplset"], v["gb"], v["radiance"], v["params"])
-    assert best in (1, 2, 4, 8)
+    assert best in (1, 2, 4, 8, 16)
     n = vplg.vplset_count(ctx, v["vplset"])
     assert vplg.autotune_lookup(ctx, v["gb"].width, v["gb"].height, n) == best
     path = os.path.join(tmp_path, "tune.txt")
     vplg.autotune_save(ctx, path)
     c2 = vplg.context_create(0)
     try:
-        assert vplg.autotune_lookup(c2, v["gb"].width, v["gb"].height, n) == 8
+        # untuned: the tile-count rule (16 waves below 32 tiles per compute unit, else 8)
+        tiles = ((v["gb"].width + 7) // 8) * ((v["gb"].height + 7) // 8)
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        assert vplg.autotune_lookup(c2, v["gb"].width, v["gb"].height, n) == (16 if tiles < 32 * cus else 8)
+        assert vplg.autotune_lookup(c2, 1920, 1080, n) == (16 if 240 * 135 < 32 * cus else 8)
         vplg.autotune_load(c2, path)
         assert vplg.autotune_lookup(c2, v["gb"].width, v["gb"].height, n) == best
     finally:
