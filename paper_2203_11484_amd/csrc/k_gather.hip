@@ -221,6 +221,49 @@ __device__ __forceinline__ void child_boxes(const float4& n0, const float4& n1, 
     }
 }
 
+// Slab test of both child boxes of a node for a segment whose SlabRay is
+// rescaled to its parameter range: plane distances are u = (s - tlo) /
+// (thi - tlo), so the range is u in [0, 1].  Every distance is clamped to
+// [0, 1] (a free output modifier of the FMA), which folds in the range
+// limits: a child passes iff lo < hi, i.e. the segment crosses the box over
+// an interval of positive length.  That is the exact-range test except for
+// zero-length contacts (lo == hi), and those cannot lead to a triangle:
+// boxes are padded outward by more than the FP32 error of the plane
+// distances, so a segment through a point of a triangle crosses the box of
+// every node holding it over an interval longer than that error.  No plane
+// distance is NaN (safe_inv keeps the inverse direction finite).
+__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.f, 1.f); }
+
+template <int OCT>
+__device__ __forceinline__ void seg_boxes(const float4& n0, const float4& n1, const float4& n2, const SlabRay& r,
+                                          float* lo0, float* hi0, float* lo1, float* hi1)
+{
+    if constexpr (OCT < 8) {
+        constexpr bool nx = OCT & 1, ny = OCT & 2, nz = OCT & 4;
+        const float a0 = clamp01(fmaf(nx ? n0.y : n0.x, r.ix, -r.ox)), a1 = clamp01(fmaf(nx ? n0.x : n0.y, r.ix, -r.ox));
+        const float b0 = clamp01(fmaf(ny ? n0.w : n0.z, r.iy, -r.oy)), b1 = clamp01(fmaf(ny ? n0.z : n0.w, r.iy, -r.oy));
+        const float c0 = clamp01(fmaf(nz ? n2.y : n2.x, r.iz, -r.oz)), c1 = clamp01(fmaf(nz ? n2.x : n2.y, r.iz, -r.oz));
+        *lo0 = fmaxf(fmaxf(a0, b0), c0);
+        *hi0 = fminf(fminf(a1, b1), c1);
+        const float d0 = clamp01(fmaf(nx ? n1.y : n1.x, r.ix, -r.ox)), d1 = clamp01(fmaf(nx ? n1.x : n1.y, r.ix, -r.ox));
+        const float e0 = clamp01(fmaf(ny ? n1.w : n1.z, r.iy, -r.oy)), e1 = clamp01(fmaf(ny ? n1.z : n1.w, r.iy, -r.oy));
+        const float f0 = clamp01(fmaf(nz ? n2.w : n2.z, r.iz, -r.oz)), f1 = clamp01(fmaf(nz ? n2.z : n2.w, r.iz, -r.oz));
+        *lo1 = fmaxf(fmaxf(d0, e0), f0);
+        *hi1 = fminf(fminf(d1, e1), f1);
+    } else {
+        const float a0 = clamp01(fmaf(n0.x, r.ix, -r.ox)), a1 = clamp01(fmaf(n0.y, r.ix, -r.ox));
+        const float b0 = clamp01(fmaf(n0.z, r.iy, -r.oy)), b1 = clamp01(fmaf(n0.w, r.iy, -r.oy));
+        const float c0 = clamp01(fmaf(n2.x, r.iz, -r.oz)), c1 = clamp01(fmaf(n2.y, r.iz, -r.oz));
+        *lo0 = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fminf(c0, c1));
+        *hi0 = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fmaxf(c0, c1));
+        const float d0 = clamp01(fmaf(n1.x, r.ix, -r.ox)), d1 = clamp01(fmaf(n1.y, r.ix, -r.ox));
+        const float e0 = clamp01(fmaf(n1.z, r.iy, -r.oy)), e1 = clamp01(fmaf(n1.w, r.iy, -r.oy));
+        const float f0 = clamp01(fmaf(n2.z, r.iz, -r.oz)), f1 = clamp01(fmaf(n2.w, r.iz, -r.oz));
+        *lo1 = fmaxf(fmaxf(fminf(d0, d1), fminf(e0, e1)), fminf(f0, f1));
+        *hi1 = fminf(fminf(fmaxf(d0, d1), fmaxf(e0, e1)), fmaxf(f0, f1));
+    }
+}
+
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ bool lane_bit(unsigned long long m, int lane) { return (m >> lane) & 1ull; }
@@ -270,9 +313,9 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
         if (COUNT && lane_bit(alive, lane)) cnt.nodes++;
         if (COUNT && lane == 0) cnt.psteps++;
         float lo0, hi0, lo1, hi1;
-        child_boxes<OCT>(n0, n1, n2, r, tlo, thi, &lo0, &hi0, &lo1, &hi1);
-        unsigned long long b0 = ballot(lo0 <= hi0) & alive;
-        unsigned long long b1 = ballot(lo1 <= hi1) & alive;
+        seg_boxes<OCT>(n0, n1, n2, r, &lo0, &hi0, &lo1, &hi1);
+        unsigned long long b0 = ballot(lo0 < hi0) & alive;
+        unsigned long long b1 = ballot(lo1 < hi1) & alive;
         if (kk != 0) {
             // a leaf child is tested at once and never entered
             const int k0 = kk & 0xffff, k1 = kk >> 16;
@@ -320,13 +363,16 @@ template <bool COUNT>
 __device__ __forceinline__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz, float dx, float dy, float dz,
                                bool act, float tlo, float thi, int ex0, int ex1, int lane, Counters& cnt)
 {
+    // slab distances in units of the segment's range: u = (s - tlo) * us
+    const float us = 1.0f / (thi - tlo);
+    const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
     SlabRay r;
-    r.ix = safe_inv(dx);
-    r.iy = safe_inv(dy);
-    r.iz = safe_inv(dz);
-    r.ox = ox * r.ix;
-    r.oy = oy * r.iy;
-    r.oz = oz * r.iz;
+    r.ix = ix * us;
+    r.iy = iy * us;
+    r.iz = iz * us;
+    r.ox = fmaf(ox, ix, tlo) * us;
+    r.oy = fmaf(oy, iy, tlo) * us;
+    r.oz = fmaf(oz, iz, tlo) * us;
     WtRay wr = wt_ray(ox, oy, oz, dx, dy, dz);
     const float4* __restrict__ nodes = sc.nodes;
     const float4* __restrict__ tris = sc.tris;
