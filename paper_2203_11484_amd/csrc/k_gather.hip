@@ -119,11 +119,14 @@ __device__ __forceinline__ WtRay wt_ray(float ox, float oy, float oz, float dx, 
 // as fmaf.
 struct TriEval {
     float U, V, W, det, t, inv;
+    float akz, bkz, ckz;  // vertex depths along the dominant axis, relative to the origin
     bool steep;
     int id;
 };
 
-__device__ __forceinline__ TriEval tri_eval(const Rec& rec, const WtRay& r)
+// First half of the test: the edge functions U, V, W (their signs decide
+// whether the ray's line crosses the triangle).
+__device__ __forceinline__ TriEval tri_edges(const Rec& rec, const WtRay& r)
 {
     const float4 q0 = rec.q0, q1 = rec.q1, q2 = rec.q2;
     TriEval e;
@@ -162,12 +165,27 @@ __device__ __forceinline__ TriEval tri_eval(const Rec& rec, const WtRay& r)
     e.U = U;
     e.V = V;
     e.W = W;
-    e.det = U + V + W;
+    e.akz = akz;
+    e.bkz = bkz;
+    e.ckz = ckz;
+    return e;
+}
+
+// Second half: determinant, hit parameter and the parallel-ray cut.
+__device__ __forceinline__ void tri_finish(TriEval& e, const Rec& rec, const WtRay& r)
+{
+    e.det = e.U + e.V + e.W;
     // t = T / det with T = sz (U a_kz + V b_kz + W c_kz)
-    const float T = fmaf(W, ckz, fmaf(V, bkz, U * akz));
+    const float T = fmaf(e.W, e.ckz, fmaf(e.V, e.bkz, e.U * e.akz));
     e.inv = rcpf(e.det);
     e.t = T * (r.sz * e.inv);
-    e.steep = e.det * e.det > q1.w * r.q;
+    e.steep = e.det * e.det > rec.q1.w * r.q;
+}
+
+__device__ __forceinline__ TriEval tri_eval(const Rec& rec, const WtRay& r)
+{
+    TriEval e = tri_edges(rec, r);
+    tri_finish(e, rec, r);
     return e;
 }
 
@@ -280,15 +298,19 @@ __device__ __forceinline__ unsigned long long leaf_any_hit(const float4* __restr
     for (int i = first; i < first + count; ++i) {
         if (COUNT && lane_bit(enter & alive, lane)) cnt.tris++;
         if (COUNT && lane == 0) cnt.ptris++;
-        const TriEval e = tri_eval(load_rec(tris, i), wr);
-        // lanes whose segment is blocked: the masks of the single conditions
-        // combine on the scalar unit
-        const unsigned long long inside = ballot(fminf(fminf(e.U, e.V), e.W) >= 0.f) |
-                                          ballot(fmaxf(fmaxf(e.U, e.V), e.W) <= 0.f);
+        const Rec rec = load_rec(tris, i);
+        if (__float_as_int(rec.q0.w) == ex1) continue;  // the VPL's own triangle
+        TriEval e = tri_edges(rec, wr);
+        // lanes whose line crosses the triangle; the masks of the single
+        // conditions combine on the scalar unit
+        const unsigned long long inside = (ballot(fminf(fminf(e.U, e.V), e.W) >= 0.f) |
+                                           ballot(fmaxf(fmaxf(e.U, e.V), e.W) <= 0.f)) & enter & alive;
+        // most tests end here: no entering lane's line crosses the triangle
+        if (inside == 0) continue;
+        tri_finish(e, rec, wr);
         // steep implies det != 0 (det^2 > cut q > 0)
-        unsigned long long blocked = inside & ballot(e.steep) & ballot(e.t > tlo) & ballot(e.t < thi) &
-                                     ballot(e.id != ex0) & enter;
-        if (e.id == ex1) blocked = 0;  // the VPL's own triangle
+        const unsigned long long blocked = inside & ballot(e.steep) & ballot(e.t > tlo) & ballot(e.t < thi) &
+                                           ballot(e.id != ex0);
         alive &= ~blocked;
         if ((alive & enter) == 0) break;
     }
