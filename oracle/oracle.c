@@ -742,10 +742,56 @@ enum {
     ST_B1, ST_B2, ST_B3, ST_FLAGS, ST_NEAR_DISCARDED, ST_COUNT
 };
 
+/* Eq. (2)'s light factor at point y (normal nk, on triangle t): Phi-free
+ * irradiance per unit power, V cos / (4 pi r^2) for the point light, or the
+ * mean over the 16 quad cells of V cos_l cos / (pi r^2). */
+static double light_factor(const oscene* s, const olight* L, v3 y, v3 nk, int t, double eps)
+{
+    double gsum = 0.0;
+    if (L->kind == 0) {
+        v3 w = vsub(L->pos, y);
+        double r2w = vdot(w, w);
+        double r = sqrt(r2w);
+        double ck = vdot(nk, w) / r;
+        if (ck > 0.0 && visible(s, y, t, L->pos, -1, eps)) gsum = ck / ((4.0 * OR_PI) * r2w);
+    } else {
+        for (int j = 0; j < 16; j++) {
+            v3 lj = vadd(vadd(L->pos, vscl(L->eu, ((double)(j % 4) + 0.5) / 4.0)),
+                         vscl(L->ev, ((double)(j / 4) + 0.5) / 4.0));
+            v3 w = vsub(lj, y);
+            double r2w = vdot(w, w);
+            double r = sqrt(r2w);
+            double cl = -vdot(L->nl, w) / r;
+            double ck = vdot(nk, w) / r;
+            if (cl > 0.0 && ck > 0.0 && visible(s, y, t, lj, -1, eps)) gsum += (cl * ck) / (OR_PI * r2w);
+        }
+        gsum = gsum / 16.0;
+    }
+    return gsum;
+}
+
 /*
  * Full VPL generation.  cam = eye, target, up, vfov_deg, W, H; light = kind,
- * pos, edge_u, edge_v, power; ip = k_near, n_far, max_bounces, max_paths, walk_near;
- * dp = d_near, patch_h.
+ * pos, edge_u, edge_v, power; ip = k_near, n_far, max_bounces, max_paths, walk_near,
+ * jitter, brightness; dp = d_near, patch_h.
+ *
+ * Readings of the paper's generation steps (Section "Realization of VPL
+ * Generation Algorithm Based on Patch" and the flow steps (1)-(3)):
+ *   walk_near  0: every walk hit on a near patch is discarded and the path
+ *                 continues (flow step (3) as written);
+ *              1: only first-bounce near hits are discarded (later ones are
+ *                 kept as walk VPLs);
+ *              2: a near hit is discarded and ends its path.
+ *   jitter     0: stratum k's target is its midpoint floor((2k+1) f(N) / 2K);
+ *              1: the target is B_k + floor(xi_k (B_{k+1} - B_k)) with the
+ *                 stratum bounds B_k = floor(k f(N) / K) and xi_k the Halton
+ *                 base-5 value of k + 1.
+ *   brightness 0: the VPL's flux is eq. (2) at its own point with the area
+ *                 D = f(N) / K it stands for;
+ *              1: the flux is eq. (2) summed over the set of patches of its
+ *                 stratum, each patch evaluated at its centroid with the part
+ *                 of its area that lies in [B_k, B_{k+1}) (a patch spanning
+ *                 several strata shares its area among their VPLs).
  *
  * Outputs (caller-allocated):
  *   patch_off  int64 [T + 1]        first global patch index of each triangle
@@ -769,11 +815,13 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
     olight L = make_light(light);
     int K = (int)ip[0], n_far = (int)ip[1], maxb = (int)ip[2];
     int64_t max_paths = ip[3];
-    int walk_near = (int)ip[4]; /* 1: near hits after the first bounce are kept as walk VPLs */
+    int walk_near = (int)ip[4];
+    int jitter = (int)ip[5], brightness = (int)ip[6];
     double dn = dp[0], ph = dp[1];
     for (int i = 0; i < ST_COUNT; i++) stats[i] = 0;
     /* eight Halton bases: start (2 or 4 dimensions) + 2 per scatter */
     if (maxb < 1 || (L.kind == 0 ? 2 : 4) + 2 * (maxb - 1) > 8 || K < 0 || n_far < 0) return -2;
+    if (walk_near < 0 || walk_near > 2 || jitter < 0 || jitter > 1 || brightness < 0 || brightness > 1) return -2;
 
     /* step 1: refine every triangle into patches, classify near / eligible */
     int* level = (int*)malloc(sizeof(int) * (size_t)(s->T > 0 ? s->T : 1));
@@ -851,9 +899,37 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
      * D = f(N) / K that every VPL represents. */
     double D = ((double)Q * unit) / (double)K;
     int nv = 0;
+    /* brightness = 1: eq. (2)'s light factor at every eligible patch's centroid */
+    double* gpatch = NULL;
+    if (brightness && Keff > 0) {
+        gpatch = (double*)malloc(sizeof(double) * (size_t)n_el);
+        for (int64_t j = 0; j < n_el; j++) {
+            int g = kp[j].idx, t = tri_of[j], n = level[t];
+            int a, b, down;
+            local_to_ab(n, (int)(g - patch_off[t]), &a, &b, &down);
+            v3 P[3];
+            patch_verts(s, t, n, a, b, down, P);
+            v3 c = mk((P[0].x + P[1].x + P[2].x) / 3.0, (P[0].y + P[1].y + P[2].y) / 3.0,
+                      (P[0].z + P[1].z + P[2].z) / 3.0);
+            gpatch[j] = light_factor(s, &L, c, s->n[t], t, eps);
+        }
+    }
     for (int kk = 0; kk < Keff; kk++) {
-        __int128 num = (__int128)(2 * (int64_t)kk + 1) * (__int128)Q;
-        int64_t u = (int64_t)(num / (__int128)(2 * (int64_t)K));
+        /* stratum bounds B_k = floor(k f(N) / K) */
+        int64_t Bk = (int64_t)(((__int128)kk * (__int128)Q) / (__int128)K);
+        int64_t Bk1 = (int64_t)(((__int128)(kk + 1) * (__int128)Q) / (__int128)K);
+        int64_t u;
+        if (jitter) {
+            int64_t len = Bk1 - Bk, off = 0;
+            if (len > 0) {
+                off = (int64_t)floor(oracle_halton(5, kk + 1) * (double)len);
+                if (off > len - 1) off = len - 1;
+            }
+            u = Bk + off;
+        } else {
+            __int128 num = (__int128)(2 * (int64_t)kk + 1) * (__int128)Q;
+            u = (int64_t)(num / (__int128)(2 * (int64_t)K));
+        }
         int64_t lo = 0, hi = n_el; /* smallest j with F[j] > u */
         while (lo < hi) { int64_t mid = (lo + hi) / 2; if (F[mid] > u) hi = mid; else lo = mid + 1; }
         m[kk] = (int32_t)lo;
@@ -868,32 +944,31 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
         v3 y = mk(w0 * P[0].x + w1 * P[1].x + w2 * P[2].x, w0 * P[0].y + w1 * P[1].y + w2 * P[2].y,
                   w0 * P[0].z + w1 * P[1].z + w2 * P[2].z);
         v3 nk = s->n[t];
-        double gsum = 0.0;
-        if (L.kind == 0) {
-            v3 w = vsub(L.pos, y);
-            double r2w = vdot(w, w);
-            double r = sqrt(r2w);
-            double ck = vdot(nk, w) / r;
-            if (ck > 0.0 && visible(s, y, t, L.pos, -1, eps)) gsum = ck / ((4.0 * OR_PI) * r2w);
-        } else {
-            for (int j = 0; j < 16; j++) {
-                v3 lj = vadd(vadd(L.pos, vscl(L.eu, ((double)(j % 4) + 0.5) / 4.0)),
-                             vscl(L.ev, ((double)(j / 4) + 0.5) / 4.0));
-                v3 w = vsub(lj, y);
-                double r2w = vdot(w, w);
-                double r = sqrt(r2w);
-                double cl = -vdot(L.nl, w) / r;
-                double ck = vdot(nk, w) / r;
-                if (cl > 0.0 && ck > 0.0 && visible(s, y, t, lj, -1, eps)) gsum += (cl * ck) / (OR_PI * r2w);
-            }
-            gsum = gsum / 16.0;
-        }
         vpl_pos[3 * nv] = y.x; vpl_pos[3 * nv + 1] = y.y; vpl_pos[3 * nv + 2] = y.z;
         vpl_nrm[3 * nv] = nk.x; vpl_nrm[3 * nv + 1] = nk.y; vpl_nrm[3 * nv + 2] = nk.z;
-        for (int c = 0; c < 3; c++) {
-            double E = L.power[c] * gsum;
-            double phi = (s->rho[3 * t + c] * E) * D;
-            vpl_I[3 * nv + c] = phi / OR_PI;
+        if (!brightness) {
+            double gsum = light_factor(s, &L, y, nk, t, eps);
+            for (int c = 0; c < 3; c++) {
+                double E = L.power[c] * gsum;
+                double phi = (s->rho[3 * t + c] * E) * D;
+                vpl_I[3 * nv + c] = phi / OR_PI;
+            }
+        } else {
+            /* eq. (2) over the stratum's set of patches, in sorted order, each
+             * with the part of its area inside [B_k, B_{k+1}) */
+            double phi[3] = {0.0, 0.0, 0.0};
+            int64_t j = 0, hj = n_el; /* first patch with F[j] > B_k */
+            while (j < hj) { int64_t mid = (j + hj) / 2; if (F[mid] > Bk) hj = mid; else j = mid + 1; }
+            for (; j < n_el; j++) {
+                int64_t f0 = j > 0 ? F[j - 1] : 0, f1 = F[j];
+                if (f0 >= Bk1) break;
+                int64_t ov = (f1 < Bk1 ? f1 : Bk1) - (f0 > Bk ? f0 : Bk);
+                if (ov <= 0) continue;
+                int tj = tri_of[j];
+                double A = (double)ov * unit;
+                for (int c = 0; c < 3; c++) phi[c] += (s->rho[3 * tj + c] * (L.power[c] * gpatch[j])) * A;
+            }
+            for (int c = 0; c < 3; c++) vpl_I[3 * nv + c] = phi[c] / OR_PI;
         }
         vpl_tri[nv] = t;
         vpl_path[nv] = 0;
@@ -908,7 +983,8 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
      * n_far_t; fluxes are then divided by the number of paths.  Variant
      * walk_near = 1 (not the paper's reading): only first-bounce near hits,
      * the light the patch VPLs stand for, are discarded; later near hits
-     * become walk VPLs and count toward n_far_t. */
+     * become walk VPLs and count toward n_far_t; walk_near = 2: a near hit
+     * ends its path. */
     int base_far = nv;
     int64_t path = 0;
     int nfar = 0;
@@ -954,8 +1030,8 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
             if (a + b > n - 1) a = n - 1 - b;
             int down = (a + b <= n - 2) && ((U - (double)a) + (V - (double)b) > 1.0);
             int64_t g = patch_off[t] + (int64_t)b * (2 * n - b) + 2 * a + down;
-            if (!(pflags[g] & 1) || (walk_near && bnc >= 2)) {
-                if (nv >= cap) { free(level); free(kp); free(tri_of); return -1; }
+            if (!(pflags[g] & 1) || (walk_near == 1 && bnc >= 2)) {
+                if (nv >= cap) { free(level); free(kp); free(tri_of); free(gpatch); return -1; }
                 vpl_pos[3 * nv] = y.x; vpl_pos[3 * nv + 1] = y.y; vpl_pos[3 * nv + 2] = y.z;
                 vpl_nrm[3 * nv] = s->n[t].x; vpl_nrm[3 * nv + 1] = s->n[t].y; vpl_nrm[3 * nv + 2] = s->n[t].z;
                 for (int c = 0; c < 3; c++) vpl_I[3 * nv + c] = flux[c]; /* normalised below */
@@ -967,6 +1043,7 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
                 nfar++;
             } else {
                 stats[ST_NEAR_DISCARDED]++;
+                if (walk_near == 2) break; /* the near hit ends the path */
             }
             if (bnc == maxb) break;
             double s1 = oracle_halton(PRIMES[dim], path), s2 = oracle_halton(PRIMES[dim + 1], path);
@@ -987,6 +1064,7 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
     free(level);
     free(kp);
     free(tri_of);
+    free(gpatch);
     return nv;
 }
 

@@ -223,7 +223,8 @@ class Scene:
     def generate(self, cam, light, params):
         p = params
         ca, la = cam_array(cam), light_array(light)
-        ip = np.array([p["k_near"], p["n_far"], p["max_bounces"], p["max_paths"], p.get("walk_near", 0)], np.int64)
+        ip = np.array([p["k_near"], p["n_far"], p["max_bounces"], p["max_paths"], p.get("walk_near", 0),
+                       p.get("jitter", 0), p.get("brightness", 0)], np.int64)
         dp = np.array([p["d_near"], p["patch_h"]], np.float64)
         NP = int(lib().oracle_patch_count(self.h, float(p["patch_h"])))
         cap = int(p["k_near"] + p["n_far"])
