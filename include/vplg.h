@@ -143,14 +143,24 @@ int vplg_gbuffer_render(vplg_context* ctx, uint64_t scene_id, const vplg_camera*
  * patch_h    faces are refined into patches with edges <= patch_h
  * t_eps      shadow-ray segment trim, as in the gather
  * walk_near  0: the paper's flow step (3), every walk hit on a near patch is
- *            discarded; 1 (a variant, not the paper's reading): only
+ *            discarded and the path continues; 1 (a variant): only
  *            first-bounce near hits are discarded (the patch VPLs stand for
  *            that light), later near hits become walk VPLs and count toward
- *            n_far.  Any other value is EINVAL.                              */
+ *            n_far; 2 (a variant): a near hit is discarded and ends its path.
+ * jitter     0: stratum k's target is its midpoint floor((2k+1) f(N) / 2K);
+ *            1: B_k + floor(xi_k (B_{k+1} - B_k)) with the stratum bounds
+ *            B_k = floor(k f(N) / K) and xi_k the base-5 radical inverse of
+ *            k + 1 (jittered strata).
+ * brightness 0: a patch VPL's flux is eq. (2) at its own point with the area
+ *            f(N) / K it stands for; 1: eq. (2) summed over the set of
+ *            patches of its stratum (the passage's "set of triangles"), each
+ *            at its centroid with the part of its area inside
+ *            [B_k, B_{k+1}), so a patch spanning several strata is shared.
+ * Values outside these ranges are EINVAL.                                   */
 typedef struct {
     int32_t k_near, n_far, max_bounces, max_paths;
     double d_near, patch_h, t_eps;
-    int32_t walk_near;
+    int32_t walk_near, jitter, brightness;
 } vplg_gen_params;
 
 typedef struct {

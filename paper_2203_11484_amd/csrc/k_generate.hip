@@ -6,12 +6,16 @@
 //      d_near; eligible = near and facing the light
 //   3. order eligible patches by (Morton key of the centroid, patch index)
 //   4. fixed-point area prefix f(i); K strata of [0, f(N)] with midpoint
-//      targets; inverse CDF picks the patch of each VPL
+//      targets (or, jitter = 1, targets jittered inside the integer stratum
+//      bounds B_k = floor(k f(N) / K)); inverse CDF picks the patch of each VPL
 //   5. place the VPL with the square-root triangle formula at Halton
-//      (2, 3)(k + 1), brightness from eq. (2) with area f(N)/K
+//      (2, 3)(k + 1), brightness from eq. (2) with area f(N)/K (or,
+//      brightness = 1, eq. (2) summed over the stratum's patches at their
+//      centroids, each with its area inside [B_k, B_{k+1}))
 //   6. sparse quasi-random walk from the light; hits on far patches become
-//      VPLs, hits on near patches are discarded (in the walk_near variant
-//      only at the first bounce), until n_far VPLs exist
+//      VPLs, hits on near patches are discarded (walk_near = 1: only at the
+//      first bounce; walk_near = 2: the near hit ends its path), until n_far
+//      VPLs exist
 //
 // Integer outcomes (levels, flags, order, strata, hit triangles, path
 // counts) are decided in FP64 with a fixed operation order so that a plain
@@ -457,6 +461,52 @@ __global__ void k_sorted_areas(DevScene s, GenParams p, GenBuffers b, long long*
     q[j] = (long long)round(area / unit);
 }
 
+// Eq. (2)'s light factor at point y (normal nk, on triangle t) per unit
+// power: V cos / (4 pi r^2) for the point light, or the mean over the 16
+// quad cells of V cos_l cos / (pi r^2).
+__device__ double light_factor64(const DevScene& s, const Light64& L, d3 y, d3 nk, int t, double t_eps)
+{
+    double gsum = 0.0;
+    if (L.kind == 0) {
+        d3 w = sub(L.pos, y);
+        double r2w = dot(w, w);
+        double r = sqrt(r2w);
+        double ck = dot(nk, w) / r;
+        if (ck > 0.0 && visible64(s, y, t, L.pos, -1, t_eps)) gsum = ck / ((4.0 * kPi) * r2w);
+    } else {
+        for (int j = 0; j < 16; ++j) {
+            d3 lj = add(add(L.pos, scl(L.eu, ((double)(j % 4) + 0.5) / 4.0)), scl(L.ev, ((double)(j / 4) + 0.5) / 4.0));
+            d3 w = sub(lj, y);
+            double r2w = dot(w, w);
+            double r = sqrt(r2w);
+            double cl = -dot(L.nl, w) / r;
+            double ck = dot(nk, w) / r;
+            if (cl > 0.0 && ck > 0.0 && visible64(s, y, t, lj, -1, t_eps)) gsum += (cl * ck) / (kPi * r2w);
+        }
+        gsum = gsum / 16.0;
+    }
+    return gsum;
+}
+
+// brightness = 1: the light factor at the centroid of every eligible patch,
+// in sorted order (runs after k_sorted_areas: patch_g reuses the sort buffer).
+__global__ void k_patch_light(DevScene s, DevLight dl, GenParams p, GenBuffers b)
+{
+    long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= b.state->n_eligible) return;
+    int g = b.sorted[j];
+    int t = tri_of_patch(b.patch_off, s.n_tris, g);
+    int n = b.level[t];
+    int a, bb, down;
+    local_to_ab(n, (int)(g - b.patch_off[t]), &a, &bb, &down);
+    d3 A = vA(s, t);
+    d3 e1 = sub(vB(s, t), A), e2 = sub(vC(s, t), A);
+    d3 P[3];
+    patch_verts(A, e1, e2, n, a, bb, down, P);
+    d3 c = mk((P[0].x + P[1].x + P[2].x) / 3.0, (P[0].y + P[1].y + P[2].y) / 3.0, (P[0].z + P[1].z + P[2].z) / 3.0);
+    b.patch_g[j] = light_factor64(s, light64(dl), c, norm(cross(e1, e2)), t, p.t_eps);
+}
+
 __global__ void k_strata_state(GenParams p, GenBuffers b)
 {
     // q_total, k_eff and the far target, once the prefix is known.
@@ -477,7 +527,20 @@ __global__ void k_strata(DevScene s, DevLight dl, GenParams p, GenBuffers b, Dev
     long long Q = b.state->q_total;
     long long ne = b.state->n_eligible;
     long long K = p.k_near;
-    long long u = ((2 * (long long)kk + 1) * Q) / (2 * K);
+    // stratum bounds B_k = floor(k f(N) / K) (k Q fits: (2K + 1) Q does)
+    const long long Bk = ((long long)kk * Q) / K, Bk1 = ((long long)(kk + 1) * Q) / K;
+    long long u;
+    if (p.jitter) {
+        const long long len = Bk1 - Bk;
+        long long off = 0;
+        if (len > 0) {
+            off = (long long)floor(halton(5, kk + 1) * (double)len);
+            if (off > len - 1) off = len - 1;
+        }
+        u = Bk + off;
+    } else {
+        u = ((2 * (long long)kk + 1) * Q) / (2 * K);
+    }
     long long lo = 0, hi = ne;  // smallest j with F[j] > u
     while (lo < hi) {
         long long mid = (lo + hi) >> 1;
@@ -500,33 +563,38 @@ __global__ void k_strata(DevScene s, DevLight dl, GenParams p, GenBuffers b, Dev
               w0 * P[0].z + w1 * P[1].z + w2 * P[2].z);
     d3 nk = norm(cross(e1, e2));
     Light64 L = light64(dl);
-    double D = ((double)Q * ((p.patch_h * p.patch_h) * 0x1p-24)) / (double)K;
-    double gsum = 0.0;
-    if (L.kind == 0) {
-        d3 w = sub(L.pos, y);
-        double r2w = dot(w, w);
-        double r = sqrt(r2w);
-        double ck = dot(nk, w) / r;
-        if (ck > 0.0 && visible64(s, y, t, L.pos, -1, p.t_eps)) gsum = ck / ((4.0 * kPi) * r2w);
-    } else {
-        for (int j = 0; j < 16; ++j) {
-            d3 lj = add(add(L.pos, scl(L.eu, ((double)(j % 4) + 0.5) / 4.0)), scl(L.ev, ((double)(j / 4) + 0.5) / 4.0));
-            d3 w = sub(lj, y);
-            double r2w = dot(w, w);
-            double r = sqrt(r2w);
-            double cl = -dot(L.nl, w) / r;
-            double ck = dot(nk, w) / r;
-            if (cl > 0.0 && ck > 0.0 && visible64(s, y, t, lj, -1, p.t_eps)) gsum += (cl * ck) / (kPi * r2w);
-        }
-        gsum = gsum / 16.0;
-    }
     v.px[kk] = (float)y.x; v.py[kk] = (float)y.y; v.pz[kk] = (float)y.z;
     v.nx[kk] = (float)nk.x; v.ny[kk] = (float)nk.y; v.nz[kk] = (float)nk.z;
     float* outs[3] = {v.ir, v.ig, v.ib};
-    for (int c = 0; c < 3; ++c) {
-        double E = L.power[c] * gsum;
-        double phi = ((double)s.albedo[3 * t + c] * E) * D;
-        outs[c][kk] = (float)(phi / kPi);
+    const double unit = (p.patch_h * p.patch_h) * 0x1p-24;
+    if (!p.brightness) {
+        double D = ((double)Q * unit) / (double)K;
+        double gsum = light_factor64(s, L, y, nk, t, p.t_eps);
+        for (int c = 0; c < 3; ++c) {
+            double E = L.power[c] * gsum;
+            double phi = ((double)s.albedo[3 * t + c] * E) * D;
+            outs[c][kk] = (float)(phi / kPi);
+        }
+    } else {
+        // eq. (2) over the stratum's patches in sorted order, each with the
+        // part of its fixed-point area inside [B_k, B_{k+1})
+        double phi[3] = {0.0, 0.0, 0.0};
+        long long j = 0, hj = ne;  // first patch with F[j] > B_k
+        while (j < hj) {
+            long long mid = (j + hj) >> 1;
+            if (b.F[mid] > Bk) hj = mid; else j = mid + 1;
+        }
+        for (; j < ne; ++j) {
+            const long long f0 = j > 0 ? b.F[j - 1] : 0, f1 = b.F[j];
+            if (f0 >= Bk1) break;
+            const long long ov = (f1 < Bk1 ? f1 : Bk1) - (f0 > Bk ? f0 : Bk);
+            if (ov <= 0) continue;
+            const int tj = tri_of_patch(b.patch_off, s.n_tris, b.sorted[j]);
+            const double A = (double)ov * unit;
+            const double gj = b.patch_g[j];
+            for (int c = 0; c < 3; ++c) phi[c] += ((double)s.albedo[3 * tj + c] * (L.power[c] * gj)) * A;
+        }
+        for (int c = 0; c < 3; ++c) outs[c][kk] = (float)(phi[c] / kPi);
     }
     v.tri[kk] = t;
     b.vpl_path[kk] = 0;
@@ -584,7 +652,7 @@ __global__ void k_walk(DevScene s, DevLight dl, GenParams p, GenBuffers b, long 
         if (a + bb > n - 1) a = n - 1 - bb;
         int down = (a + bb <= n - 2) && ((U - (double)a) + (V - (double)bb) > 1.0);
         long long g = b.patch_off[t] + (long long)bb * (2 * n - bb) + 2 * a + down;
-        if (!(b.pflags[g] & 1) || (p.walk_near && bnc >= 2)) {
+        if (!(b.pflags[g] & 1) || (p.walk_near == 1 && bnc >= 2)) {
             int slot = i * 3 + cnt;
             b.w_pos[3 * slot] = y.x; b.w_pos[3 * slot + 1] = y.y; b.w_pos[3 * slot + 2] = y.z;
             for (int c = 0; c < 3; ++c) b.w_flux[3 * slot + c] = flux[c];
@@ -593,6 +661,7 @@ __global__ void k_walk(DevScene s, DevLight dl, GenParams p, GenBuffers b, long 
             cnt++;
         } else {
             discard_mask |= 1 << (bnc - 1);
+            if (p.walk_near == 2) break;  // the near hit ends the path
         }
         if (bnc == p.max_bounces) break;
         double s1 = halton(prime(dim), path), s2 = halton(prime(dim + 1), path);
@@ -856,6 +925,9 @@ hipError_t launch_generate(const DevScene& sc, const DevLight& L, const CamBasis
     }
     GenBuffers bb = b;
     bb.F = b.scan_out + 1;
+    bb.patch_g = reinterpret_cast<double*>(b.sortbuf);
+    if (p.brightness && p.k_near > 0 && NP > 0)
+        hipLaunchKernelGGL(k_patch_light, dim3(nblocks(NP, GB)), dim3(GB), 0, s, sc, L, p, bb);
     hipLaunchKernelGGL(k_strata_state, dim3(1), dim3(1), 0, s, p, bb);
     if (p.k_near > 0) hipLaunchKernelGGL(k_strata, dim3(nblocks(p.k_near, 64)), dim3(64), 0, s, sc, L, p, bb, v);
     // the walk: batches of growing size until the far target is met or

@@ -414,7 +414,9 @@ int check_gen_params(const vplg_gen_params* p)
     if (!(p->patch_h > 0.0) || !std::isfinite(p->patch_h)) return fail(VPLG_EINVAL, "patch_h must be > 0");
     if (!(p->d_near >= 0.0)) return fail(VPLG_EINVAL, "d_near must be >= 0");
     if (!(p->t_eps >= 0.0 && p->t_eps < 0.5)) return fail(VPLG_EINVAL, "t_eps must be in [0, 0.5)");
-    if (p->walk_near != 0 && p->walk_near != 1) return fail(VPLG_EINVAL, "walk_near must be 0 or 1");
+    if (p->walk_near < 0 || p->walk_near > 2) return fail(VPLG_EINVAL, "walk_near must be 0, 1 or 2");
+    if (p->jitter != 0 && p->jitter != 1) return fail(VPLG_EINVAL, "jitter must be 0 or 1");
+    if (p->brightness != 0 && p->brightness != 1) return fail(VPLG_EINVAL, "brightness must be 0 or 1");
     return VPLG_OK;
 }
 
@@ -547,7 +549,8 @@ int alloc_genset(vplg_context* ctx, SceneObj* so, uint64_t scene_id, PatchIndex*
 int launch_genset(SceneObj* so, VplSetObj* v, const vplg_camera* cam, const vplg_gen_params* p, hipStream_t s)
 {
     CamBasis cb = cam_basis(cam);
-    GenParams gp{p->k_near, p->n_far, p->max_bounces, p->max_paths, p->d_near, p->patch_h, p->t_eps, p->walk_near};
+    GenParams gp{p->k_near,    p->n_far,   p->max_bounces, p->max_paths, p->d_near,
+                 p->patch_h,   p->t_eps,   p->walk_near,   p->jitter,    p->brightness};
     HIPCHK(launch_generate(so->dev, so->light, cb, gp, v->dev, v->gen, s));
     HIPCHK(launch_pack_vpls(v->dev, s));
     HIPCHK(hipEventRecord(v->done, s));

@@ -151,7 +151,9 @@ struct CamBasis {
 struct GenParams {
     int k_near, n_far, max_bounces, max_paths;
     double d_near, patch_h, t_eps;
-    int walk_near;  // 1: near hits after the first bounce become walk VPLs
+    int walk_near;   // 1: near hits after the first bounce become walk VPLs; 2: a near hit ends its path
+    int jitter;      // 1: stratum targets jittered by the base-5 radical inverse of k + 1
+    int brightness;  // 1: a patch VPL's flux is eq. (2) summed over its stratum's patches
 };
 
 // Device-side record of one generation (counts are int64).
@@ -170,6 +172,7 @@ struct GenBuffers {
     long long* patch_off;   // [T + 1]
     uint8_t* pflags;        // [n_patches]
     unsigned long long* sortbuf;  // [pow2 >= n_patches] (key << 32 | patch)
+    double* patch_g;        // = sortbuf once the order is extracted: eq. (2)'s light factor per sorted patch
     int32_t* sorted;        // [n_patches]
     uint32_t* keys;         // [n_patches]
     long long* F;           // [n_patches]

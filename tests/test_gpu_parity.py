@@ -198,13 +198,20 @@ def test_gbuffer_parity(vplg, ctx):
         vplg.scene_release(ctx, sid)
 
 
-@pytest.mark.parametrize("name,walk_near", [("cornell", 0), ("room20k", 0), ("room200k", 0), ("cornell", 1),
-                                             ("room20k", 1)])
-def test_generation_parity(vplg, ctx, name, walk_near):
+GEN_VARIANTS = [("cornell", {}), ("room20k", {}), ("room200k", {}), ("cornell", {"walk_near": 1}),
+                ("room20k", {"walk_near": 1}), ("cornell", {"walk_near": 2}), ("room20k", {"walk_near": 2}),
+                ("cornell", {"jitter": 1}), ("cornell", {"brightness": 1}), ("room20k", {"jitter": 1, "brightness": 1}),
+                ("room200k", {"brightness": 1})]
+
+
+@pytest.mark.parametrize("name,variant", GEN_VARIANTS,
+                         ids=[f"{n}-" + ("-".join(f"{k}{v}" for k, v in d.items()) or "paper") for n, d in GEN_VARIANTS])
+def test_generation_parity(vplg, ctx, name, variant):
     """Every integer output of the generation bit-exact at the workloads' full sizes, for the paper's
-    walk and for the variant that keeps near hits after the first bounce."""
+    reading and for each variant (walk: near hits kept after the first bounce, or ending the path;
+    jittered strata; brightness summed over the stratum's patches)."""
     sc = scenes.make_scene(name)
-    prm = dict(sc["params"], walk_near=walk_near)
+    prm = dict(sc["params"], **variant)
     S = orc.Scene.from_dict(sc)
     ref = S.generate(sc["camera"], sc["light"], prm)
     sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
@@ -261,9 +268,8 @@ def test_abi_errors(vplg, ctx):
     finally:
         vplg.context_destroy(tiny)
     sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
-    p = dict(sc["params"])
-    p["max_bounces"] = 5
-    with pytest.raises(vplg.VplgError) as e:
-        vplg.vpls_generate(ctx, sid, sc["camera"], p)
-    assert e.value.code == vplg.EINVAL
+    for bad in ({"max_bounces": 5}, {"walk_near": 3}, {"walk_near": -1}, {"jitter": 2}, {"brightness": -1}):
+        with pytest.raises(vplg.VplgError) as e:
+            vplg.vpls_generate(ctx, sid, sc["camera"], dict(sc["params"], **bad))
+        assert e.value.code == vplg.EINVAL, bad
     vplg.scene_release(ctx, sid)
