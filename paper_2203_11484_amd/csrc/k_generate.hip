@@ -211,34 +211,69 @@ __device__ __forceinline__ bool tri64(const DevScene& s, int t, d3 o, d3 d, doub
     return true;
 }
 
-__device__ __forceinline__ bool box64(double lx, double hx, double ly, double hy, double lz, double hz, d3 o, d3 d,
-                                      double tmin, double tmax)
+constexpr int kStack64 = kStack + 2;
+// The FP64 traversals keep their stacks in LDS, [entry][thread] for kGenBlock
+// threads (one per lane: entries of a lane are kGenBlock words apart, so the
+// lanes of a wave hit distinct banks).  Private arrays would live in scratch,
+// and the waves that may hold scratch at once are capped: a launch of many
+// traversing waves would run a few at a time.
+constexpr int kGenBlock = 64;
+struct LdsStack {
+    int* base;  // &stack[0][thread]
+    __device__ __forceinline__ int& operator[](int i) const { return base[i * kGenBlock]; }
+};
+#define VPLG_LDS_STACK(name)                                   \
+    __shared__ int name##_mem[kStack64 * kGenBlock];          \
+    const LdsStack name{name##_mem + threadIdx.x}
+
+// Per-ray inverse direction for the FP64 slab tests; an axis with a zero
+// component is flagged and tested by containment instead.
+struct Inv64 {
+    double o[3], inv[3];
+    bool zero[3];
+};
+
+__device__ __forceinline__ Inv64 inv64(d3 o, d3 d)
 {
-    double oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
-    double lo[3] = {lx, ly, lz}, hi[3] = {hx, hy, hz};
+    Inv64 r;
+    const double oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
+    for (int k = 0; k < 3; ++k) {
+        r.o[k] = oo[k];
+        r.zero[k] = dd[k] == 0.0;
+        r.inv[k] = r.zero[k] ? 0.0 : 1.0 / dd[k];
+    }
+    return r;
+}
+
+// Entry parameter of the ray into the box within (tmin, tmax), or +inf if
+// it misses.  Plane distances are (plane - o) * (1 / d): within an ulp of
+// the quotient, far inside the boxes' outward padding, so no box that holds
+// a hit inside (tmin, tmax) is culled and the hit found is the same.
+__device__ __forceinline__ double slab64(double lx, double hx, double ly, double hy, double lz, double hz,
+                                         const Inv64& r, double tmin, double tmax)
+{
+    const double lo[3] = {lx, ly, lz}, hi[3] = {hx, hy, hz};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        if (dd[k] == 0.0) {
-            if (oo[k] < lo[k] || oo[k] > hi[k]) return false;
+        if (r.zero[k]) {
+            if (r.o[k] < lo[k] || r.o[k] > hi[k]) return __builtin_inf();
             continue;
         }
-        double t0 = (lo[k] - oo[k]) / dd[k], t1 = (hi[k] - oo[k]) / dd[k];
+        double t0 = (lo[k] - r.o[k]) * r.inv[k], t1 = (hi[k] - r.o[k]) * r.inv[k];
         if (t0 > t1) { double tmp = t0; t0 = t1; t1 = tmp; }
         tmin = t0 > tmin ? t0 : tmin;
         tmax = t1 < tmax ? t1 : tmax;
-        if (tmin > tmax) return false;
+        if (tmin > tmax) return __builtin_inf();
     }
-    return true;
+    return tmin;
 }
 
-constexpr int kStack64 = kStack + 2;
-
 // Visibility (segment, s in (eps, 1 - eps), host triangles tx / ty skipped).
-__device__ bool visible64(const DevScene& s, d3 x, int tx, d3 y, int ty, double eps)
+__device__ bool visible64(const DevScene& s, d3 x, int tx, d3 y, int ty, double eps, LdsStack stack)
 {
     d3 d = sub(y, x);
     double lo = eps, hi = 1.0 - eps;
-    int stack[kStack64];
+    const Inv64 ri = inv64(x, d);
     int sp = 0;
     stack[sp++] = 0;
     while (sp > 0) {
@@ -249,9 +284,9 @@ __device__ bool visible64(const DevScene& s, d3 x, int tx, d3 y, int ty, double 
         const int kk = __float_as_int(n3f.z);
         int k[2] = {kk & 0xffff, kk >> 16};
         for (int ch = 0; ch < 2; ++ch) {
-            bool h = ch == 0 ? box64(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, x, d, lo, hi)
-                             : box64(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, x, d, lo, hi);
-            if (!h) continue;
+            const double e = ch == 0 ? slab64(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, ri, lo, hi)
+                                     : slab64(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, ri, lo, hi);
+            if (!(e < __builtin_inf())) continue;
             if (k[ch] > 0) {
                 for (int i = c[ch]; i < c[ch] + k[ch]; ++i) {
                     int t = __float_as_int(s.tris[kTriStride * i].w);
@@ -270,36 +305,46 @@ __device__ bool visible64(const DevScene& s, d3 x, int tx, d3 y, int ty, double 
 // Closest hit with t in (tmin, inf), ties to the smaller triangle index;
 // triangle ex and (if skip_emit) emitters are skipped.
 __device__ int closest64(const DevScene& s, d3 o, d3 d, double tmin, int ex, bool skip_emit, double* tb, double* ub,
-                         double* vb)
+                         double* vb, LdsStack stack)
 {
     int best = -1;
     double bt = __builtin_inf(), bu = 0, bv = 0;
-    int stack[kStack64];
+    const Inv64 ri = inv64(o, d);
     int sp = 0;
     stack[sp++] = 0;
     while (sp > 0) {
         int node = stack[--sp];
         const float4* n = s.nodes + 4 * node;
         float4 n0 = n[0], n1 = n[1], n2 = n[2], n3f = n[3];
-        int c[2] = {__float_as_int(n3f.x), __float_as_int(n3f.y)};
+        const int c[2] = {__float_as_int(n3f.x), __float_as_int(n3f.y)};
         const int kk = __float_as_int(n3f.z);
-        int k[2] = {kk & 0xffff, kk >> 16};
+        const int k[2] = {kk & 0xffff, kk >> 16};
+        double e[2] = {slab64(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, ri, tmin, bt),
+                       slab64(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, ri, tmin, bt)};
+        // leaf children first (their hits shrink bt), then the inner
+        // children, the nearer one on top of the stack; a child is entered
+        // iff the ray meets its box within (tmin, bt] (a miss is +inf)
         for (int ch = 0; ch < 2; ++ch) {
-            bool h = ch == 0 ? box64(n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, o, d, tmin, bt)
-                             : box64(n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, o, d, tmin, bt);
-            if (!h) continue;
-            if (k[ch] > 0) {
-                for (int i = c[ch]; i < c[ch] + k[ch]; ++i) {
-                    int t = __float_as_int(s.tris[kTriStride * i].w);
-                    double tt, u, v;
-                    if (t == ex || (skip_emit && (s.flags[t] & 1))) continue;
-                    if (tri64(s, t, o, d, &tt, &u, &v) && tt > tmin) {
-                        if (best < 0 || tt < bt || (tt == bt && t < best)) { best = t; bt = tt; bu = u; bv = v; }
-                    }
+            if (k[ch] == 0 || !(e[ch] < __builtin_inf() && e[ch] <= bt)) continue;
+            for (int i = c[ch]; i < c[ch] + k[ch]; ++i) {
+                int t = __float_as_int(s.tris[kTriStride * i].w);
+                double tt, u, v;
+                if (t == ex || (skip_emit && (s.flags[t] & 1))) continue;
+                if (tri64(s, t, o, d, &tt, &u, &v) && tt > tmin) {
+                    if (best < 0 || tt < bt || (tt == bt && t < best)) { best = t; bt = tt; bu = u; bv = v; }
                 }
-            } else {
-                stack[sp++] = c[ch];
             }
+        }
+        const bool in0 = k[0] == 0 && e[0] < __builtin_inf() && e[0] <= bt;
+        const bool in1 = k[1] == 0 && e[1] < __builtin_inf() && e[1] <= bt;
+        if (in0 && in1) {
+            const bool near0 = e[0] <= e[1];
+            stack[sp++] = near0 ? c[1] : c[0];
+            stack[sp++] = near0 ? c[0] : c[1];
+        } else if (in0) {
+            stack[sp++] = c[0];
+        } else if (in1) {
+            stack[sp++] = c[1];
         }
     }
     *tb = bt; *ub = bu; *vb = bv;
@@ -464,7 +509,8 @@ __global__ void k_sorted_areas(DevScene s, GenParams p, GenBuffers b, long long*
 // Eq. (2)'s light factor at point y (normal nk, on triangle t) per unit
 // power: V cos / (4 pi r^2) for the point light, or the mean over the 16
 // quad cells of V cos_l cos / (pi r^2).
-__device__ double light_factor64(const DevScene& s, const Light64& L, d3 y, d3 nk, int t, double t_eps)
+__device__ double light_factor64(const DevScene& s, const Light64& L, d3 y, d3 nk, int t, double t_eps,
+                                 LdsStack stk)
 {
     double gsum = 0.0;
     if (L.kind == 0) {
@@ -472,7 +518,7 @@ __device__ double light_factor64(const DevScene& s, const Light64& L, d3 y, d3 n
         double r2w = dot(w, w);
         double r = sqrt(r2w);
         double ck = dot(nk, w) / r;
-        if (ck > 0.0 && visible64(s, y, t, L.pos, -1, t_eps)) gsum = ck / ((4.0 * kPi) * r2w);
+        if (ck > 0.0 && visible64(s, y, t, L.pos, -1, t_eps, stk)) gsum = ck / ((4.0 * kPi) * r2w);
     } else {
         for (int j = 0; j < 16; ++j) {
             d3 lj = add(add(L.pos, scl(L.eu, ((double)(j % 4) + 0.5) / 4.0)), scl(L.ev, ((double)(j / 4) + 0.5) / 4.0));
@@ -481,7 +527,7 @@ __device__ double light_factor64(const DevScene& s, const Light64& L, d3 y, d3 n
             double r = sqrt(r2w);
             double cl = -dot(L.nl, w) / r;
             double ck = dot(nk, w) / r;
-            if (cl > 0.0 && ck > 0.0 && visible64(s, y, t, lj, -1, t_eps)) gsum += (cl * ck) / (kPi * r2w);
+            if (cl > 0.0 && ck > 0.0 && visible64(s, y, t, lj, -1, t_eps, stk)) gsum += (cl * ck) / (kPi * r2w);
         }
         gsum = gsum / 16.0;
     }
@@ -490,8 +536,9 @@ __device__ double light_factor64(const DevScene& s, const Light64& L, d3 y, d3 n
 
 // brightness = 1: the light factor at the centroid of every eligible patch,
 // in sorted order (runs after k_sorted_areas: patch_g reuses the sort buffer).
-__global__ void k_patch_light(DevScene s, DevLight dl, GenParams p, GenBuffers b)
+__global__ __launch_bounds__(kGenBlock) void k_patch_light(DevScene s, DevLight dl, GenParams p, GenBuffers b)
 {
+    VPLG_LDS_STACK(stk);
     long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= b.state->n_eligible) return;
     int g = b.sorted[j];
@@ -504,7 +551,7 @@ __global__ void k_patch_light(DevScene s, DevLight dl, GenParams p, GenBuffers b
     d3 P[3];
     patch_verts(A, e1, e2, n, a, bb, down, P);
     d3 c = mk((P[0].x + P[1].x + P[2].x) / 3.0, (P[0].y + P[1].y + P[2].y) / 3.0, (P[0].z + P[1].z + P[2].z) / 3.0);
-    b.patch_g[j] = light_factor64(s, light64(dl), c, norm(cross(e1, e2)), t, p.t_eps);
+    b.patch_g[j] = light_factor64(s, light64(dl), c, norm(cross(e1, e2)), t, p.t_eps, stk);
 }
 
 __global__ void k_strata_state(GenParams p, GenBuffers b)
@@ -520,8 +567,9 @@ __global__ void k_strata_state(GenParams p, GenBuffers b)
 }
 
 // One VPL per stratum: midpoint target, inverse CDF, placement, eq. (2).
-__global__ void k_strata(DevScene s, DevLight dl, GenParams p, GenBuffers b, DevVpls v)
+__global__ __launch_bounds__(kGenBlock) void k_strata(DevScene s, DevLight dl, GenParams p, GenBuffers b, DevVpls v)
 {
+    VPLG_LDS_STACK(stk);
     int kk = blockIdx.x * blockDim.x + threadIdx.x;
     if (kk >= b.state->k_eff || (b.state->flags & 2)) return;
     long long Q = b.state->q_total;
@@ -569,7 +617,7 @@ __global__ void k_strata(DevScene s, DevLight dl, GenParams p, GenBuffers b, Dev
     const double unit = (p.patch_h * p.patch_h) * 0x1p-24;
     if (!p.brightness) {
         double D = ((double)Q * unit) / (double)K;
-        double gsum = light_factor64(s, L, y, nk, t, p.t_eps);
+        double gsum = light_factor64(s, L, y, nk, t, p.t_eps, stk);
         for (int c = 0; c < 3; ++c) {
             double E = L.power[c] * gsum;
             double phi = ((double)s.albedo[3 * t + c] * E) * D;
@@ -602,8 +650,10 @@ __global__ void k_strata(DevScene s, DevLight dl, GenParams p, GenBuffers b, Dev
 }
 
 // One thread per walk path of the batch [start + 1, start + batch].
-__global__ void k_walk(DevScene s, DevLight dl, GenParams p, GenBuffers b, long long start, int nb)
+__global__ __launch_bounds__(kGenBlock) void k_walk(DevScene s, DevLight dl, GenParams p, GenBuffers b, long long start,
+                                                    int nb)
 {
+    VPLG_LDS_STACK(stk);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb || b.state->walk_done) return;
     long long path = start + i + 1;
@@ -633,7 +683,7 @@ __global__ void k_walk(DevScene s, DevLight dl, GenParams p, GenBuffers b, long 
     int cnt = 0, discard_mask = 0;
     for (int bnc = 1; bnc <= p.max_bounces; ++bnc) {
         double tb, u, v;
-        int t = closest64(s, o, d, 0.0, ex, skip_emit, &tb, &u, &v);
+        int t = closest64(s, o, d, 0.0, ex, skip_emit, &tb, &u, &v, stk);
         if (t < 0) break;
         if (s.flags[t] & 1) break;
         d3 A = vA(s, t);
@@ -927,16 +977,20 @@ hipError_t launch_generate(const DevScene& sc, const DevLight& L, const CamBasis
     bb.F = b.scan_out + 1;
     bb.patch_g = reinterpret_cast<double*>(b.sortbuf);
     if (p.brightness && p.k_near > 0 && NP > 0)
-        hipLaunchKernelGGL(k_patch_light, dim3(nblocks(NP, GB)), dim3(GB), 0, s, sc, L, p, bb);
+        hipLaunchKernelGGL(k_patch_light, dim3(nblocks(NP, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb);
     hipLaunchKernelGGL(k_strata_state, dim3(1), dim3(1), 0, s, p, bb);
-    if (p.k_near > 0) hipLaunchKernelGGL(k_strata, dim3(nblocks(p.k_near, 64)), dim3(64), 0, s, sc, L, p, bb, v);
+    if (p.k_near > 0)
+        hipLaunchKernelGGL(k_strata, dim3(nblocks(p.k_near, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb, v);
     // the walk: batches of growing size until the far target is met or
     // max_paths is reached (batches after that exit at once)
     hipLaunchKernelGGL(k_walk_begin, dim3(1), dim3(1), 0, s, bb);
     long long start = 0;
-    int nb = b.batch < 1024 ? b.batch : 1024;
+    // the walk is latency-bound (one serial path per thread): the first
+    // batch takes the whole capacity; deposits are kept in path order, so
+    // the batch sizes never change the result
+    int nb = b.batch;
     while (start < p.max_paths) {
-        hipLaunchKernelGGL(k_walk, dim3(nblocks(nb, 64)), dim3(64), 0, s, sc, L, p, bb, start, nb);
+        hipLaunchKernelGGL(k_walk, dim3(nblocks(nb, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb, start, nb);
         hipLaunchKernelGGL(k_walk_collect, dim3(1), dim3(COLLECT_T), 0, s, p, bb, v, start, nb);
         start += nb;
         nb = nb * 2 <= b.batch ? nb * 2 : b.batch;

@@ -117,6 +117,16 @@ def test_gather_cornell_all_pixels(vplg, ctx, size):
     print(f"cornell {size}: {nd} grazing disagreements of {n} pairs")
 
 
+@pytest.mark.parametrize("tile_vpl", [1, 2, 4, 8, 16])
+def test_gather_every_tile_shape(vplg, ctx, tile_vpl):
+    """Every waves-per-tile choice on the ragged 100 x 75 Cornell image, every pixel: only the summation
+    order across a tile's waves changes, so each must meet the same bar against the oracle."""
+    sc = scenes.make_scene("cornell", width=100, height=75)
+    S, gbo, vp, _ = _oracle_inputs(sc)
+    prm = dict(sc["params"], tile_vpl=tile_vpl)
+    _check_gather(vplg, ctx, sc, S, gbo, vp, np.arange(100 * 75), prm, f"cornell tile_vpl {tile_vpl}")
+
+
 def test_gather_room20k_sampled(vplg, ctx):
     """20k-triangle room at its full 512^2 size and 4096 VPLs; 384 sampled pixels checked pair by pair."""
     sc = scenes.make_scene("room20k")
