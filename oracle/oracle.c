@@ -742,6 +742,23 @@ enum {
     ST_B1, ST_B2, ST_B3, ST_FLAGS, ST_NEAR_DISCARDED, ST_COUNT
 };
 
+/* Mean albedo of the scene for Keller's path schedule: the face-area-weighted
+ * mean, over the faces that do not emit, of the mean of the three channels
+ * (0 when those faces have no area). */
+double oracle_rho_bar(void* h)
+{
+    const oscene* s = (const oscene*)h;
+    double num = 0.0, den = 0.0;
+    for (int t = 0; t < s->T; t++) {
+        if (s->flags[t] & 1) continue;
+        v3 cr = vcross(s->e1[t], s->e2[t]);
+        double a = 0.5 * sqrt(vdot(cr, cr));
+        num += a * (((s->rho[3 * t] + s->rho[3 * t + 1]) + s->rho[3 * t + 2]) / 3.0);
+        den += a;
+    }
+    return den > 0.0 ? num / den : 0.0;
+}
+
 /* Eq. (2)'s light factor at point y (normal nk, on triangle t): Phi-free
  * irradiance per unit power, V cos / (4 pi r^2) for the point light, or the
  * mean over the 16 quad cells of V cos_l cos / (pi r^2). */
@@ -773,7 +790,7 @@ static double light_factor(const oscene* s, const olight* L, v3 y, v3 nk, int t,
 /*
  * Full VPL generation.  cam = eye, target, up, vfov_deg, W, H; light = kind,
  * pos, edge_u, edge_v, power; ip = k_near, n_far, max_bounces, max_paths, walk_near,
- * jitter, brightness; dp = d_near, patch_h.
+ * jitter, brightness, walk_schedule; dp = d_near, patch_h.
  *
  * Readings of the paper's generation steps (Section "Realization of VPL
  * Generation Algorithm Based on Patch" and the flow steps (1)-(3)):
@@ -786,6 +803,15 @@ static double light_factor(const oscene* s, const olight* L, v3 y, v3 nk, int t,
  *              1: the target is B_k + floor(xi_k (B_{k+1} - B_k)) with the
  *                 stratum bounds B_k = floor(k f(N) / K) and xi_k the Halton
  *                 base-5 value of k + 1.
+ *   walk_schedule 0: paths run until n_far far VPLs exist (the last path
+ *                 cut there), fluxes divided by the number of paths;
+ *              1: Keller's schedule for instant radiosity: N = floor(n_far /
+ *                 sum_{j < max_bounces} rb^j) paths with rb the scene's mean
+ *                 albedo (area-weighted over the faces that do not emit, mean
+ *                 of the three channels); path i goes on to bounce b only if
+ *                 i <= floor(rb^(b-1) N), and a deposit at bounce b carries
+ *                 Phi prod(rho) / (N rb^(b-1)) (the paths that stop stand for
+ *                 the light the others carry on).
  *   brightness 0: the VPL's flux is eq. (2) at its own point with the area
  *                 D = f(N) / K it stands for;
  *              1: the flux is eq. (2) summed over the set of patches of its
@@ -816,12 +842,14 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
     int K = (int)ip[0], n_far = (int)ip[1], maxb = (int)ip[2];
     int64_t max_paths = ip[3];
     int walk_near = (int)ip[4];
-    int jitter = (int)ip[5], brightness = (int)ip[6];
+    int jitter = (int)ip[5], brightness = (int)ip[6], walk_schedule = (int)ip[7];
     double dn = dp[0], ph = dp[1];
     for (int i = 0; i < ST_COUNT; i++) stats[i] = 0;
     /* eight Halton bases: start (2 or 4 dimensions) + 2 per scatter */
     if (maxb < 1 || (L.kind == 0 ? 2 : 4) + 2 * (maxb - 1) > 8 || K < 0 || n_far < 0) return -2;
-    if (walk_near < 0 || walk_near > 2 || jitter < 0 || jitter > 1 || brightness < 0 || brightness > 1) return -2;
+    if (walk_near < 0 || walk_near > 2 || jitter < 0 || jitter > 1 || brightness < 0 || brightness > 1 ||
+        walk_schedule < 0 || walk_schedule > 1)
+        return -2;
 
     /* step 1: refine every triangle into patches, classify near / eligible */
     int* level = (int*)malloc(sizeof(int) * (size_t)(s->T > 0 ? s->T : 1));
@@ -988,8 +1016,20 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
     int base_far = nv;
     int64_t path = 0;
     int nfar = 0;
-    while (nfar < n_far_t) {
-        if (path >= max_paths) { stats[ST_FLAGS] |= 1; break; }
+    /* walk_schedule = 1: the number of paths and each bounce's path limit */
+    double rb = 0.0;
+    int64_t keller_n = 0, keller_t[3] = {0, 0, 0};
+    if (walk_schedule) {
+        rb = oracle_rho_bar((void*)s);
+        double S = 0.0, r = 1.0;
+        for (int j = 0; j < maxb; j++) { S += r; r *= rb; }
+        keller_n = (int64_t)floor((double)n_far_t / S);
+        if (keller_n > max_paths) { keller_n = max_paths; stats[ST_FLAGS] |= 1; }
+        double rr = 1.0;
+        for (int j = 0; j < maxb; j++) { keller_t[j] = (int64_t)floor(rr * (double)keller_n); rr *= rb; }
+    }
+    while (walk_schedule ? path < keller_n : nfar < n_far_t) {
+        if (!walk_schedule && path >= max_paths) { stats[ST_FLAGS] |= 1; break; }
         path++;
         int dim = 0;
         v3 o, d;
@@ -1011,13 +1051,17 @@ int oracle_generate(void* h, const double* cam, const double* light, const int64
             skip_emit = 1;
         }
         double flux[3] = {L.power[0], L.power[1], L.power[2]};
-        for (int bnc = 1; bnc <= maxb && nfar < n_far_t; bnc++) {
+        for (int bnc = 1; bnc <= maxb && (walk_schedule || nfar < n_far_t); bnc++) {
+            if (walk_schedule && path > keller_t[bnc - 1]) break;
             double tb, u, v;
             int t = closest(s, o, d, 0.0, INFINITY, ex, skip_emit, &tb, &u, &v);
             if (t < 0) break;                       /* miss */
             if (s->flags[t] & 1) break;             /* reached an emitter */
             if (!(vdot(d, s->n[t]) < 0.0)) break;   /* back side of a one-sided face */
-            for (int c = 0; c < 3; c++) flux[c] = flux[c] * s->rho[3 * t + c];
+            for (int c = 0; c < 3; c++) {
+                flux[c] = flux[c] * s->rho[3 * t + c];
+                if (walk_schedule && bnc >= 2) flux[c] = flux[c] / rb;
+            }
             v3 y = vadd(vadd(s->A[t], vscl(s->e1[t], u)), vscl(s->e2[t], v));
             /* the patch of the hit point, from its barycentric coordinates */
             int n = level[t];

@@ -53,6 +53,8 @@ def lib():
         L.oracle_direct.argtypes = [_p, _p, _p, _p, _p, C.c_int64, _p, C.c_double, _p, _p, _p, C.c_int64, _p]
         L.oracle_halton.restype = C.c_double
         L.oracle_halton.argtypes = [C.c_int, C.c_int64]
+        L.oracle_rho_bar.restype = C.c_double
+        L.oracle_rho_bar.argtypes = [_p]
         L.oracle_patch_count.restype = C.c_int64
         L.oracle_patch_count.argtypes = [_p, C.c_double]
         L.oracle_generate.restype = C.c_int
@@ -219,12 +221,16 @@ class Scene:
                                 float(eps), _ptr(out))
         return out
 
+    def rho_bar(self):
+        """The scene's mean albedo of Keller's path schedule (area-weighted over non-emitting faces)."""
+        return float(lib().oracle_rho_bar(self.h))
+
     # -- generation --------------------------------------------------------
     def generate(self, cam, light, params):
         p = params
         ca, la = cam_array(cam), light_array(light)
         ip = np.array([p["k_near"], p["n_far"], p["max_bounces"], p["max_paths"], p.get("walk_near", 0),
-                       p.get("jitter", 0), p.get("brightness", 0)], np.int64)
+                       p.get("jitter", 0), p.get("brightness", 0), p.get("walk_schedule", 0)], np.int64)
         dp = np.array([p["d_near"], p["patch_h"]], np.float64)
         NP = int(lib().oracle_patch_count(self.h, float(p["patch_h"])))
         cap = int(p["k_near"] + p["n_far"])

@@ -262,3 +262,90 @@ def test_set_sum_skips_occluded_patches():
     assert (~lit).sum() > 0 and lit.sum() > 0
     expect = sum(_point_factor((0, h, 0), c) * q * unit for c, q, L in zip(cents, qs, lit) if L)
     np.testing.assert_allclose(g["I"][0, 0] * math.pi, expect, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Keller's path schedule
+# ---------------------------------------------------------------------------
+
+def test_keller_mean_albedo():
+    """Area-weighted mean over the faces that do not emit, of the channel mean: quads of area 1 and 3 with
+    grey albedo 0.25 and 0.75 give (0.25 + 2.25) / 4 = 0.625; an emitting face does not count."""
+    a = H.floor_quad(0, 1, 0, 1)             # area 1
+    b = H.floor_quad(2, 5, 0, 1)             # area 3
+    e = H.floor_quad(0, 1, 2, 3, y=1.0)      # emitter
+    tri = np.concatenate([a, b, e])
+    alb = np.array([[0.25] * 3] * 2 + [[0.75] * 3] * 2 + [[1.0, 0.5, 0.0]] * 2, np.float32)
+    flags = np.array([0, 0, 0, 0, 1, 1], np.uint8)
+    S = orc.Scene.from_dict(H.scene_dict(tri, alb, flags=flags), use_bvh=False)
+    assert S.rho_bar() == 0.625
+
+
+def _keller_expect(rb, n_far, maxb=3):
+    S, r = 0.0, 1.0
+    for _ in range(maxb):
+        S += r
+        r *= rb
+    N = math.floor(n_far / S)
+    T, r = [], 1.0
+    for _ in range(maxb):
+        T.append(math.floor(r * N))
+        r *= rb
+    return N, T
+
+
+def test_keller_schedule_counts_and_path_limits():
+    """Closed box, every hit deposits (no near region): N = floor(n_far / (1 + rb + rb^2)) paths; path i
+    deposits at bounces 1..b with b the last bounce whose limit floor(rb^(b-1) N) admits it, so
+    bounce b holds exactly that many VPLs."""
+    sc = _closed_box_scene(0.625, n_far=500)
+    S = orc.Scene.from_dict(sc, use_bvh=False)
+    rb = S.rho_bar()
+    assert abs(rb - 0.625) < 1e-15
+    g = S.generate(sc["camera"], sc["light"], dict(sc["params"], walk_schedule=1))
+    N, T = _keller_expect(rb, 500)
+    st = g["stats"]
+    assert st["n_paths"] == N and st["flags"] == 0
+    assert [st["far_b1"], st["far_b2"], st["far_b3"]] == T
+    assert st["n_far"] == sum(T) <= 500
+    p = _paths(g)
+    assert sorted(p) == list(range(1, N + 1))
+    for path, v in p.items():
+        bmax = max(b for b in (1, 2, 3) if path <= T[b - 1])
+        assert [e[0] for e in v] == list(range(1, bmax + 1)), path
+
+
+def test_keller_schedule_flux_weights():
+    """A deposit at bounce b carries Phi rho^b / (N rb^(b-1)); each bounce's VPLs together carry about
+    Phi rho^b, the reflected power of that bounce (off by the floor of the path limit only)."""
+    sc = _closed_box_scene(0.625, n_far=500)
+    S = orc.Scene.from_dict(sc, use_bvh=False)
+    rb = S.rho_bar()
+    g = S.generate(sc["camera"], sc["light"], dict(sc["params"], walk_schedule=1))
+    N, T = _keller_expect(rb, 500)
+    PL = np.array([3.0, 2.0, 1.0])
+    phi = g["I"] * math.pi
+    for i in range(g["n"]):
+        b = int(g["bounce"][i])
+        np.testing.assert_allclose(phi[i] * N, PL * 0.625 ** b / rb ** (b - 1), rtol=1e-12)
+    for b in (1, 2, 3):
+        tot = phi[g["bounce"] == b].sum(axis=0)
+        np.testing.assert_allclose(tot, PL * 0.625 ** b, rtol=1.0 / (rb ** (b - 1) * N) + 1e-12)
+
+
+def test_keller_schedule_white_box_is_the_default_walk():
+    """Albedo 1: rb = 1, every path runs all its bounces as in the default walk, and the VPLs of each path
+    are the default walk's, bit for bit (fluxes times the path count equal)."""
+    sc = _closed_box_scene(1.0, n_far=300)
+    S = orc.Scene.from_dict(sc, use_bvh=False)
+    assert S.rho_bar() == 1.0
+    g0 = S.generate(sc["camera"], sc["light"], sc["params"])
+    gk = S.generate(sc["camera"], sc["light"], dict(sc["params"], walk_schedule=1))
+    assert gk["stats"]["n_paths"] == 100  # floor(300 / 3)
+    p0, pk = _paths(g0), _paths(gk)
+    for path in range(1, 100):
+        a, b = p0[path], pk[path]
+        assert [e[0] for e in a] == [e[0] for e in b] == [1, 2, 3]
+        for e0, ek in zip(a, b):
+            assert np.array_equal(e0[1], ek[1]) and e0[2] == ek[2]
+            np.testing.assert_allclose(e0[3], ek[3], rtol=1e-12)
