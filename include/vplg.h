@@ -151,6 +151,12 @@ int vplg_gbuffer_render(vplg_context* ctx, uint64_t scene_id, const vplg_camera*
  *            1: B_k + floor(xi_k (B_{k+1} - B_k)) with the stratum bounds
  *            B_k = floor(k f(N) / K) and xi_k the base-5 radical inverse of
  *            k + 1 (jittered strata).
+ * walk_schedule 0: paths run until n_far far VPLs exist, the last path cut
+ *            there; 1: Keller's schedule: N = floor(n_far / sum_{j<max_bounces}
+ *            rb^j) paths, rb the scene's mean albedo (area-weighted over the
+ *            faces that do not emit, mean of the channels); path i goes on to
+ *            bounce b only if i <= floor(rb^(b-1) N) and a deposit at bounce b
+ *            carries Phi prod(rho) / (N rb^(b-1)); at most n_far far VPLs.
  * brightness 0: a patch VPL's flux is eq. (2) at its own point with the area
  *            f(N) / K it stands for; 1: eq. (2) summed over the set of
  *            patches of its stratum (the passage's "set of triangles"), each
@@ -160,7 +166,7 @@ int vplg_gbuffer_render(vplg_context* ctx, uint64_t scene_id, const vplg_camera*
 typedef struct {
     int32_t k_near, n_far, max_bounces, max_paths;
     double d_near, patch_h, t_eps;
-    int32_t walk_near, jitter, brightness;
+    int32_t walk_near, jitter, brightness, walk_schedule;
 } vplg_gen_params;
 
 typedef struct {

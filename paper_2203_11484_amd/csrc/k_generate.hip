@@ -554,7 +554,7 @@ __global__ __launch_bounds__(kGenBlock) void k_patch_light(DevScene s, DevLight 
     b.patch_g[j] = light_factor64(s, light64(dl), c, norm(cross(e1, e2)), t, p.t_eps, stk);
 }
 
-__global__ void k_strata_state(GenParams p, GenBuffers b)
+__global__ void k_strata_state(GenParams p, GenBuffers b, double rho_bar)
 {
     // q_total, k_eff and the far target, once the prefix is known.
     long long ne = b.state->n_eligible;
@@ -564,6 +564,17 @@ __global__ void k_strata_state(GenParams p, GenBuffers b)
     b.state->n_far_target = p.n_far + (Q > 0 ? 0 : p.k_near);
     // (2K + 1) Q must fit in int64 for the midpoint targets
     if (Q > 0 && Q > 0x7fffffffffffffffll / (2ll * p.k_near + 1)) b.state->flags |= 2;
+    if (p.walk_schedule) {
+        // Keller's schedule: N = floor(target / sum_j rb^j) paths, bounce b
+        // open to paths i <= floor(rb^(b-1) N)
+        double S = 0.0, r = 1.0;
+        for (int j = 0; j < p.max_bounces; ++j) { S += r; r *= rho_bar; }
+        long long N = (long long)floor((double)b.state->n_far_target / S);
+        if (N > p.max_paths) { N = p.max_paths; b.state->flags |= 1; }
+        b.state->keller_n = N;
+        double rr = 1.0;
+        for (int j = 0; j < p.max_bounces; ++j) { b.state->keller_t[j] = (long long)floor(rr * (double)N); rr *= rho_bar; }
+    }
 }
 
 // One VPL per stratum: midpoint target, inverse CDF, placement, eq. (2).
@@ -658,7 +669,7 @@ __global__ __launch_bounds__(kGenBlock) void k_walk(DevScene s, DevLight dl, Gen
     if (i >= nb || b.state->walk_done) return;
     long long path = start + i + 1;
     b.w_count[i] = 0;
-    if (path > p.max_paths || (b.state->flags & 2)) return;
+    if (path > (p.walk_schedule ? b.state->keller_n : (long long)p.max_paths) || (b.state->flags & 2)) return;
     Light64 L = light64(dl);
     int dim;
     d3 o, d;
@@ -681,7 +692,9 @@ __global__ __launch_bounds__(kGenBlock) void k_walk(DevScene s, DevLight dl, Gen
     }
     double flux[3] = {L.power[0], L.power[1], L.power[2]};
     int cnt = 0, discard_mask = 0;
+    const double rb = s.rho_bar;
     for (int bnc = 1; bnc <= p.max_bounces; ++bnc) {
+        if (p.walk_schedule && path > b.state->keller_t[bnc - 1]) break;
         double tb, u, v;
         int t = closest64(s, o, d, 0.0, ex, skip_emit, &tb, &u, &v, stk);
         if (t < 0) break;
@@ -690,7 +703,10 @@ __global__ __launch_bounds__(kGenBlock) void k_walk(DevScene s, DevLight dl, Gen
         d3 e1 = sub(vB(s, t), A), e2 = sub(vC(s, t), A);
         d3 nt = norm(cross(e1, e2));
         if (!(dot(d, nt) < 0.0)) break;
-        for (int c = 0; c < 3; ++c) flux[c] = flux[c] * (double)s.albedo[3 * t + c];
+        for (int c = 0; c < 3; ++c) {
+            flux[c] = flux[c] * (double)s.albedo[3 * t + c];
+            if (p.walk_schedule && bnc >= 2) flux[c] = flux[c] / rb;
+        }
         d3 y = add(add(A, scl(e1, u)), scl(e2, v));
         int n = b.level[t];
         double U = u * (double)n, V = v * (double)n;
@@ -737,7 +753,8 @@ __global__ __launch_bounds__(COLLECT_T) void k_walk_collect(GenParams p, GenBuff
     GenState* st = b.state;
     if (st->walk_done) return;
     const long long have = st->n_far;
-    const long long need = st->n_far_target;
+    // Keller's schedule keeps every deposit of its N paths (at most the target)
+    const long long need = p.walk_schedule ? 0x7fffffffffffffffll : st->n_far_target;
     const int t = threadIdx.x;
     if (t < 3) s_far[t] = 0;
     if (t == 0) { s_disc = 0; s_cut = -1; }
@@ -798,9 +815,10 @@ __global__ __launch_bounds__(COLLECT_T) void k_walk_collect(GenParams p, GenBuff
         } else {
             long long end = start + nb;
             st->n_far = have + total;
-            if (end >= p.max_paths) {
-                st->n_paths = p.max_paths;
-                st->flags |= 1;
+            const long long cap = p.walk_schedule ? st->keller_n : (long long)p.max_paths;
+            if (end >= cap) {
+                st->n_paths = cap;
+                if (!p.walk_schedule) st->flags |= 1;
                 st->walk_done = 1;
             } else {
                 st->n_paths = end;
@@ -849,6 +867,7 @@ __global__ void k_state_init(GenBuffers b, long long n_patches)
     st->n_near = st->n_eligible = st->q_total = st->k_eff = st->n_far_target = st->n_far = st->n_paths = 0;
     st->far_b[0] = st->far_b[1] = st->far_b[2] = 0;
     st->flags = st->near_discarded = 0;
+    st->keller_n = st->keller_t[0] = st->keller_t[1] = st->keller_t[2] = 0;
     st->walk_done = 0;
 }
 
@@ -978,7 +997,7 @@ hipError_t launch_generate(const DevScene& sc, const DevLight& L, const CamBasis
     bb.patch_g = reinterpret_cast<double*>(b.sortbuf);
     if (p.brightness && p.k_near > 0 && NP > 0)
         hipLaunchKernelGGL(k_patch_light, dim3(nblocks(NP, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb);
-    hipLaunchKernelGGL(k_strata_state, dim3(1), dim3(1), 0, s, p, bb);
+    hipLaunchKernelGGL(k_strata_state, dim3(1), dim3(1), 0, s, p, bb, sc.rho_bar);
     if (p.k_near > 0)
         hipLaunchKernelGGL(k_strata, dim3(nblocks(p.k_near, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb, v);
     // the walk: batches of growing size until the far target is met or

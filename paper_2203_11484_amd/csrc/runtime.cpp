@@ -235,6 +235,27 @@ int vplg_context_usage(vplg_context* ctx, uint64_t* used, uint64_t* budget)
     return VPLG_OK;
 }
 
+// Mean albedo of Keller's path schedule: face-area-weighted over the faces
+// that do not emit, of the mean of the three channels (0 without such area).
+// FP64 in triangle order; built without contraction.
+static double mean_albedo(const float* xyz, const float* alb, const uint8_t* flags, int T)
+{
+    double num = 0.0, den = 0.0;
+    for (int t = 0; t < T; ++t) {
+        if (flags[t] & 1) continue;
+        const float* p = xyz + 9 * (size_t)t;
+        const double e1[3] = {(double)p[3] - (double)p[0], (double)p[4] - (double)p[1], (double)p[5] - (double)p[2]};
+        const double e2[3] = {(double)p[6] - (double)p[0], (double)p[7] - (double)p[1], (double)p[8] - (double)p[2]};
+        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                              e1[0] * e2[1] - e1[1] * e2[0]};
+        const double a = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        const double m = (((double)alb[3 * t] + (double)alb[3 * t + 1]) + (double)alb[3 * t + 2]) / 3.0;
+        num += a * m;
+        den += a;
+    }
+    return den > 0.0 ? num / den : 0.0;
+}
+
 int vplg_scene_upload(vplg_context* ctx, const float* tri_xyz, const float* tri_albedo, const uint8_t* tri_flags,
                       int32_t n_tris, const vplg_light* light, void* stream, uint64_t* scene_id)
 {
@@ -314,6 +335,7 @@ int vplg_scene_upload(vplg_context* ctx, const float* tri_xyz, const float* tri_
     d.albedo = dalb;
     d.flags = dfl;
     d.normals = dnorm;
+    d.rho_bar = mean_albedo(tri_xyz, tri_albedo, tri_flags, n_tris);
     so->light.kind = light->kind;
     for (int k = 0; k < 3; ++k) {
         so->light.pos[k] = light->pos[k];
@@ -417,6 +439,7 @@ int check_gen_params(const vplg_gen_params* p)
     if (p->walk_near < 0 || p->walk_near > 2) return fail(VPLG_EINVAL, "walk_near must be 0, 1 or 2");
     if (p->jitter != 0 && p->jitter != 1) return fail(VPLG_EINVAL, "jitter must be 0 or 1");
     if (p->brightness != 0 && p->brightness != 1) return fail(VPLG_EINVAL, "brightness must be 0 or 1");
+    if (p->walk_schedule != 0 && p->walk_schedule != 1) return fail(VPLG_EINVAL, "walk_schedule must be 0 or 1");
     return VPLG_OK;
 }
 
@@ -549,8 +572,8 @@ int alloc_genset(vplg_context* ctx, SceneObj* so, uint64_t scene_id, PatchIndex*
 int launch_genset(SceneObj* so, VplSetObj* v, const vplg_camera* cam, const vplg_gen_params* p, hipStream_t s)
 {
     CamBasis cb = cam_basis(cam);
-    GenParams gp{p->k_near,    p->n_far,   p->max_bounces, p->max_paths, p->d_near,
-                 p->patch_h,   p->t_eps,   p->walk_near,   p->jitter,    p->brightness};
+    GenParams gp{p->k_near,  p->n_far,     p->max_bounces, p->max_paths,  p->d_near,       p->patch_h,
+                 p->t_eps,   p->walk_near, p->jitter,      p->brightness, p->walk_schedule};
     HIPCHK(launch_generate(so->dev, so->light, cb, gp, v->dev, v->gen, s));
     HIPCHK(launch_pack_vpls(v->dev, s));
     HIPCHK(hipEventRecord(v->done, s));

@@ -52,6 +52,7 @@ struct DevScene {
     const uint8_t* flags = nullptr;   // [T]
     const float4* normals = nullptr;  // [T] unit face normal (float32 of the FP64 value)
     float lo[3], hi[3];               // scene bounding box (unpadded)
+    double rho_bar = 0.0;             // mean albedo (area-weighted, non-emitting faces) for Keller's schedule
 };
 
 struct DevLight {
@@ -154,6 +155,7 @@ struct GenParams {
     int walk_near;   // 1: near hits after the first bounce become walk VPLs; 2: a near hit ends its path
     int jitter;      // 1: stratum targets jittered by the base-5 radical inverse of k + 1
     int brightness;  // 1: a patch VPL's flux is eq. (2) summed over its stratum's patches
+    int walk_schedule;  // 1: Keller's schedule (N paths, path i goes on to bounce b iff i <= floor(rb^(b-1) N))
 };
 
 // Device-side record of one generation (counts are int64).
@@ -161,6 +163,7 @@ struct GenState {
     long long n_patches, n_near, n_eligible, q_total, k_eff, n_far_target, n_far, n_paths;
     long long far_b[3];
     long long flags, near_discarded;
+    long long keller_n, keller_t[3];  // walk_schedule = 1: paths, and the path limit of each bounce
     int walk_done;
     int pad;
 };

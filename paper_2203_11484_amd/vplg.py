@@ -54,7 +54,7 @@ class GBufferStruct(C.Structure):
 class GenParams(C.Structure):
     _fields_ = [("k_near", C.c_int32), ("n_far", C.c_int32), ("max_bounces", C.c_int32), ("max_paths", C.c_int32),
                 ("d_near", C.c_double), ("patch_h", C.c_double), ("t_eps", C.c_double), ("walk_near", C.c_int32),
-                ("jitter", C.c_int32), ("brightness", C.c_int32)]
+                ("jitter", C.c_int32), ("brightness", C.c_int32), ("walk_schedule", C.c_int32)]
 
 
 class GenStats(C.Structure):
@@ -206,6 +206,7 @@ def make_gen_params(p):
     g.walk_near = int(p.get("walk_near", 0))
     g.jitter = int(p.get("jitter", 0))
     g.brightness = int(p.get("brightness", 0))
+    g.walk_schedule = int(p.get("walk_schedule", 0))
     return g
 
 

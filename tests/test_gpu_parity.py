@@ -211,7 +211,9 @@ def test_gbuffer_parity(vplg, ctx):
 GEN_VARIANTS = [("cornell", {}), ("room20k", {}), ("room200k", {}), ("cornell", {"walk_near": 1}),
                 ("room20k", {"walk_near": 1}), ("cornell", {"walk_near": 2}), ("room20k", {"walk_near": 2}),
                 ("cornell", {"jitter": 1}), ("cornell", {"brightness": 1}), ("room20k", {"jitter": 1, "brightness": 1}),
-                ("room200k", {"brightness": 1})]
+                ("room200k", {"brightness": 1}), ("cornell", {"walk_schedule": 1}),
+                ("room20k", {"walk_schedule": 1}), ("room20k", {"walk_schedule": 1, "walk_near": 1}),
+                ("cornell", {"walk_schedule": 1, "d_near": 0.0})]
 
 
 @pytest.mark.parametrize("name,variant", GEN_VARIANTS,
@@ -278,7 +280,8 @@ def test_abi_errors(vplg, ctx):
     finally:
         vplg.context_destroy(tiny)
     sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
-    for bad in ({"max_bounces": 5}, {"walk_near": 3}, {"walk_near": -1}, {"jitter": 2}, {"brightness": -1}):
+    for bad in ({"max_bounces": 5}, {"walk_near": 3}, {"walk_near": -1}, {"jitter": 2}, {"brightness": -1},
+                {"walk_schedule": 2}):
         with pytest.raises(vplg.VplgError) as e:
             vplg.vpls_generate(ctx, sid, sc["camera"], dict(sc["params"], **bad))
         assert e.value.code == vplg.EINVAL, bad
