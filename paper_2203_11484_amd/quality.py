@@ -7,10 +7,11 @@ given quality 2-5 times faster.  Here:
 
 * the reference is the gather of eq. (1) over a plain instant-radiosity VPL set of `ref_vpls`
   VPLs: the generation with d_near = 0 has no near patches, so every walk hit becomes a VPL;
-* "plain IR at M" is the same with M VPLs; "hybrid at M" is the paper's method with the workload's
-  near:far split of M, in the paper's reading (`paper`) and in the variants of the generation
-  (`VARIANTS`: near walk hits kept after the first bounce, a near hit ending its path, brightness
-  summed over the stratum's patches, jittered strata);
+* "plain IR at M" is the same with M VPLs (`ir`; `ir_keller`: Keller's path schedule, at most M
+  VPLs); "hybrid at M" is the paper's method with the workload's near:far split of M, in the paper's
+  reading (`paper`) and in the variants of the generation (`VARIANTS`: near walk hits kept after the
+  first bounce, a near hit ending its path, brightness summed over the stratum's patches, jittered
+  strata, Keller's path schedule with the near hits kept after the first bounce);
 * RMSE is taken over the pixels with a hit, all three channels, of the indirect images only
   (the direct term is left out, as in the paper's statistics);
 * a sweep renders every method at a geometric grid of VPL counts, timing generation and gather with
@@ -33,6 +34,7 @@ VARIANTS = {
     "set_sum": {"brightness": 1},
     "set_sum_walk_near1": {"brightness": 1, "walk_near": 1},
     "jitter": {"jitter": 1},
+    "keller": {"walk_schedule": 1, "walk_near": 1},
 }
 
 DEFAULT_COUNTS = (256, 512, 1024, 2048, 4096, 5120, 8192, 16384, 32768, 65536)
@@ -53,17 +55,19 @@ def rmse(a, b, mask=None):
     return float(math.sqrt(np.mean((a - b) ** 2)))
 
 
-def plain_ir_params(params, n_vpls):
-    """Plain instant radiosity with n_vpls VPLs: no near region, every walk hit deposits."""
+def plain_ir_params(params, n_vpls, walk_schedule=0):
+    """Plain instant radiosity with n_vpls VPLs: no near region, every walk hit deposits (with
+    walk_schedule = 1 in Keller's path schedule, at most n_vpls VPLs)."""
     p = dict(params)
-    p.update(k_near=0, n_far=int(n_vpls), d_near=0.0, walk_near=0, jitter=0, brightness=0)
+    p.update(k_near=0, n_far=int(n_vpls), d_near=0.0, walk_near=0, jitter=0, brightness=0,
+             walk_schedule=int(walk_schedule))
     p["max_paths"] = 64 * int(n_vpls) + 1024
     return p
 
 
 def hybrid_params(params, n_vpls, walk_near=0, **variant):
     """The hybrid method with n_vpls VPLs, split near:far as in `params`, with generation switches."""
-    p = dict(params, walk_near=walk_near, jitter=0, brightness=0)
+    p = dict(params, walk_near=walk_near, jitter=0, brightness=0, walk_schedule=0)
     p.update(variant)
     k, f = params["k_near"], params["n_far"]
     near = int(round(n_vpls * k / float(k + f)))
@@ -162,7 +166,8 @@ def sweep(vplg, ctx, scene, counts=DEFAULT_COUNTS, ref_vpls=262144, variants=VAR
         r.indirect(plain_ir_params(scene["params"], counts[0]))
         ref, n_ref, _, ref_ms = r.indirect(plain_ir_params(scene["params"], ref_vpls), timed=True)
         ref_rms = rmse(ref, np.zeros_like(ref), r.mask)
-        methods = {"ir": lambda m: plain_ir_params(scene["params"], m)}
+        methods = {"ir": lambda m: plain_ir_params(scene["params"], m),
+                   "ir_keller": lambda m: plain_ir_params(scene["params"], m, walk_schedule=1)}
         for name, var in variants.items():
             methods[name] = (lambda m, var=var: hybrid_params(scene["params"], m, **var))
         out = {"scene": scene.get("name", "?"), "reference_vpls": int(n_ref), "reference_gather_ms": ref_ms,

@@ -64,9 +64,13 @@ def sweep():
 
 
 def test_sweep_times_and_counts(sweep):
-    """Every method makes the VPLs it was asked for and its gather time grows with the count."""
+    """Every method makes the VPLs it was asked for (Keller's schedule: at most that many) and its gather
+    time grows with the count."""
     for name, d in sweep["methods"].items():
-        assert d["vpls"] == list(sweep["counts"]), name
+        if name in ("ir_keller", "keller"):
+            assert all(0.5 * c <= n <= c for n, c in zip(d["vpls"], sweep["counts"])), (name, d["vpls"])
+        else:
+            assert d["vpls"] == list(sweep["counts"]), name
         assert all(t > 0 for t in d["gather_ms"] + d["gen_ms"]), name
         assert d["gather_ms"][-1] > d["gather_ms"][0], name
 
