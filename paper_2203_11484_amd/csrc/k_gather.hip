@@ -206,37 +206,21 @@ struct SlabRay {
     float ix, iy, iz, ox, oy, oz;  // inverse direction and origin * inverse
 };
 
-// Slab test of both child boxes of a node.  OCT < 8: every ray of the packet
-// has direction signs OCT (bit a set: inverse direction on axis a is
-// negative), so the entry plane of each slab is known; OCT == 8: any signs.
-template <int OCT>
+// Slab test of both child boxes of a node for a ray with parameter range
+// (tlo, thi) and any direction signs (the G-buffer's primary rays).
 __device__ __forceinline__ void child_boxes(const float4& n0, const float4& n1, const float4& n2, const SlabRay& r,
                                             float tlo, float thi, float* lo0, float* hi0, float* lo1, float* hi1)
 {
-    if constexpr (OCT < 8) {
-        constexpr bool nx = OCT & 1, ny = OCT & 2, nz = OCT & 4;
-        const float a0 = fmaf(nx ? n0.y : n0.x, r.ix, -r.ox), a1 = fmaf(nx ? n0.x : n0.y, r.ix, -r.ox);
-        const float b0 = fmaf(ny ? n0.w : n0.z, r.iy, -r.oy), b1 = fmaf(ny ? n0.z : n0.w, r.iy, -r.oy);
-        const float c0 = fmaf(nz ? n2.y : n2.x, r.iz, -r.oz), c1 = fmaf(nz ? n2.x : n2.y, r.iz, -r.oz);
-        *lo0 = fmaxf(fmaxf(a0, b0), fmaxf(c0, tlo));
-        *hi0 = fminf(fminf(a1, b1), fminf(c1, thi));
-        const float d0 = fmaf(nx ? n1.y : n1.x, r.ix, -r.ox), d1 = fmaf(nx ? n1.x : n1.y, r.ix, -r.ox);
-        const float e0 = fmaf(ny ? n1.w : n1.z, r.iy, -r.oy), e1 = fmaf(ny ? n1.z : n1.w, r.iy, -r.oy);
-        const float f0 = fmaf(nz ? n2.w : n2.z, r.iz, -r.oz), f1 = fmaf(nz ? n2.z : n2.w, r.iz, -r.oz);
-        *lo1 = fmaxf(fmaxf(d0, e0), fmaxf(f0, tlo));
-        *hi1 = fminf(fminf(d1, e1), fminf(f1, thi));
-    } else {
-        const float a0 = fmaf(n0.x, r.ix, -r.ox), a1 = fmaf(n0.y, r.ix, -r.ox);
-        const float b0 = fmaf(n0.z, r.iy, -r.oy), b1 = fmaf(n0.w, r.iy, -r.oy);
-        const float c0 = fmaf(n2.x, r.iz, -r.oz), c1 = fmaf(n2.y, r.iz, -r.oz);
-        *lo0 = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), tlo));
-        *hi0 = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), thi));
-        const float d0 = fmaf(n1.x, r.ix, -r.ox), d1 = fmaf(n1.y, r.ix, -r.ox);
-        const float e0 = fmaf(n1.z, r.iy, -r.oy), e1 = fmaf(n1.w, r.iy, -r.oy);
-        const float f0 = fmaf(n2.z, r.iz, -r.oz), f1 = fmaf(n2.w, r.iz, -r.oz);
-        *lo1 = fmaxf(fmaxf(fminf(d0, d1), fminf(e0, e1)), fmaxf(fminf(f0, f1), tlo));
-        *hi1 = fminf(fminf(fmaxf(d0, d1), fmaxf(e0, e1)), fminf(fmaxf(f0, f1), thi));
-    }
+    const float a0 = fmaf(n0.x, r.ix, -r.ox), a1 = fmaf(n0.y, r.ix, -r.ox);
+    const float b0 = fmaf(n0.z, r.iy, -r.oy), b1 = fmaf(n0.w, r.iy, -r.oy);
+    const float c0 = fmaf(n2.x, r.iz, -r.oz), c1 = fmaf(n2.y, r.iz, -r.oz);
+    *lo0 = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), tlo));
+    *hi0 = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), thi));
+    const float d0 = fmaf(n1.x, r.ix, -r.ox), d1 = fmaf(n1.y, r.ix, -r.ox);
+    const float e0 = fmaf(n1.z, r.iy, -r.oy), e1 = fmaf(n1.w, r.iy, -r.oy);
+    const float f0 = fmaf(n2.z, r.iz, -r.oz), f1 = fmaf(n2.w, r.iz, -r.oz);
+    *lo1 = fmaxf(fmaxf(fminf(d0, d1), fminf(e0, e1)), fmaxf(fminf(f0, f1), tlo));
+    *hi1 = fminf(fminf(fmaxf(d0, d1), fmaxf(e0, e1)), fminf(fmaxf(f0, f1), thi));
 }
 
 // Slab test of both child boxes of a node for a segment whose SlabRay is
@@ -743,7 +727,7 @@ __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
         const int kk = __float_as_int(n3f.z);
         int k0 = kk & 0xffff, k1 = kk >> 16;
         float lo0, hi0, lo1, hi1;
-        child_boxes<8>(n0, n1, n2, r, 0.0f, best, &lo0, &hi0, &lo1, &hi1);
+        child_boxes(n0, n1, n2, r, 0.0f, best, &lo0, &hi0, &lo1, &hi1);
         bool h0 = lo0 <= hi0;
         bool h1 = lo1 <= hi1;
         for (int c = 0; c < 2; ++c) {
