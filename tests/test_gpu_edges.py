@@ -169,3 +169,27 @@ def test_size_limits_rejected_before_device_work(vplg, ctx):
     torch.cuda.synchronize()
     vplg.vplset_release(ctx, vid)
     vplg.scene_release(ctx, s2)
+
+
+@pytest.mark.parametrize("name", ["cornell", "room20k"])
+def test_scene_describe(vplg, ctx, name):
+    """The resident scene's description: its triangle count, its bounds (the float32 vertex extremes,
+    exactly), a BVH2 with both children present (inner nodes = leaves - 1, or one root over a single
+    leaf), the depth limit, and device bytes that the context's usage accounts for."""
+    sc = scenes.make_scene(name, width=8, height=8)
+    used0 = vplg.context_usage(ctx)[0]
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
+    d = vplg.scene_describe(ctx, sid)
+    assert d["n_tris"] == len(sc["tri"])
+    v = sc["tri"].reshape(-1, 3)
+    assert d["lo"] == v.min(axis=0).tolist() and d["hi"] == v.max(axis=0).tolist()
+    assert 1 <= d["n_leaves"] <= d["n_tris"]
+    assert d["n_nodes"] == max(1, d["n_leaves"] - 1)
+    assert 1 <= d["max_depth"] <= 47
+    assert d["device_bytes"] > 64 * d["n_tris"]
+    assert vplg.context_usage(ctx)[0] - used0 >= d["device_bytes"]
+    vplg.scene_release(ctx, sid)
+    assert vplg.context_usage(ctx)[0] == used0
+    with pytest.raises(vplg.VplgError) as e:
+        vplg.scene_describe(ctx, sid)
+    assert e.value.code == vplg.ENOTFOUND
