@@ -534,24 +534,75 @@ __device__ double light_factor64(const DevScene& s, const Light64& L, d3 y, d3 n
     return gsum;
 }
 
+// The term of light sample j in light_factor64's sum (0 when it does not
+// count): the lanes of a group evaluate one sample each, and the group's
+// first lane adds them in sample order, which reproduces the sequential sum
+// bit for bit (adding an exact 0 leaves a sum unchanged).
+__device__ double light_term64(const DevScene& s, const Light64& L, d3 y, d3 nk, int t, double t_eps, int j,
+                               LdsStack stk)
+{
+    if (L.kind == 0) {
+        d3 w = sub(L.pos, y);
+        double r2w = dot(w, w);
+        double r = sqrt(r2w);
+        double ck = dot(nk, w) / r;
+        return ck > 0.0 && visible64(s, y, t, L.pos, -1, t_eps, stk) ? ck / ((4.0 * kPi) * r2w) : 0.0;
+    }
+    d3 lj = add(add(L.pos, scl(L.eu, ((double)(j % 4) + 0.5) / 4.0)), scl(L.ev, ((double)(j / 4) + 0.5) / 4.0));
+    d3 w = sub(lj, y);
+    double r2w = dot(w, w);
+    double r = sqrt(r2w);
+    double cl = -dot(L.nl, w) / r;
+    double ck = dot(nk, w) / r;
+    return cl > 0.0 && ck > 0.0 && visible64(s, y, t, lj, -1, t_eps, stk) ? (cl * ck) / (kPi * r2w) : 0.0;
+}
+
+// Light factor of the item of a group of S lanes (S = 16: one quad-light
+// sample per lane; S = 1: the whole sum in one lane).  Every lane of the block
+// must call it (a barrier); the result is valid in the group's first lane.
+template <int S>
+__device__ double light_factor_group(const DevScene& s, const Light64& L, d3 y, d3 nk, int t, double t_eps, bool live,
+                                     double* s_term, LdsStack stk)
+{
+    if constexpr (S == 1) {
+        return live ? light_factor64(s, L, y, nk, t, t_eps, stk) : 0.0;
+    } else {
+        const int sub = threadIdx.x % S;
+        s_term[threadIdx.x] = live ? light_term64(s, L, y, nk, t, t_eps, sub, stk) : 0.0;
+        __syncthreads();
+        double gsum = 0.0;
+        if (sub == 0)
+            for (int i = 0; i < S; ++i) gsum += s_term[threadIdx.x + i];
+        return gsum / 16.0;
+    }
+}
+
 // brightness = 1: the light factor at the centroid of every eligible patch,
 // in sorted order (runs after k_sorted_areas: patch_g reuses the sort buffer).
+template <int S>
 __global__ __launch_bounds__(kGenBlock) void k_patch_light(DevScene s, DevLight dl, GenParams p, GenBuffers b)
 {
     VPLG_LDS_STACK(stk);
-    long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= b.state->n_eligible) return;
-    int g = b.sorted[j];
-    int t = tri_of_patch(b.patch_off, s.n_tris, g);
-    int n = b.level[t];
-    int a, bb, down;
-    local_to_ab(n, (int)(g - b.patch_off[t]), &a, &bb, &down);
-    d3 A = vA(s, t);
-    d3 e1 = sub(vB(s, t), A), e2 = sub(vC(s, t), A);
-    d3 P[3];
-    patch_verts(A, e1, e2, n, a, bb, down, P);
-    d3 c = mk((P[0].x + P[1].x + P[2].x) / 3.0, (P[0].y + P[1].y + P[2].y) / 3.0, (P[0].z + P[1].z + P[2].z) / 3.0);
-    b.patch_g[j] = light_factor64(s, light64(dl), c, norm(cross(e1, e2)), t, p.t_eps, stk);
+    __shared__ double s_term[kGenBlock];
+    const long long j = (long long)blockIdx.x * (kGenBlock / S) + threadIdx.x / S;
+    const bool live = j < b.state->n_eligible;
+    d3 c = mk(0.0, 0.0, 0.0), nk = mk(0.0, 0.0, 1.0);
+    int t = 0;
+    if (live) {
+        int g = b.sorted[j];
+        t = tri_of_patch(b.patch_off, s.n_tris, g);
+        int n = b.level[t];
+        int a, bb, down;
+        local_to_ab(n, (int)(g - b.patch_off[t]), &a, &bb, &down);
+        d3 A = vA(s, t);
+        d3 e1 = sub(vB(s, t), A), e2 = sub(vC(s, t), A);
+        d3 P[3];
+        patch_verts(A, e1, e2, n, a, bb, down, P);
+        c = mk((P[0].x + P[1].x + P[2].x) / 3.0, (P[0].y + P[1].y + P[2].y) / 3.0, (P[0].z + P[1].z + P[2].z) / 3.0);
+        nk = norm(cross(e1, e2));
+    }
+    const double gsum = light_factor_group<S>(s, light64(dl), c, nk, t, p.t_eps, live, s_term, stk);
+    if (live && threadIdx.x % S == 0) b.patch_g[j] = gsum;
 }
 
 __global__ void k_strata_state(GenParams p, GenBuffers b, double rho_bar)
@@ -578,57 +629,69 @@ __global__ void k_strata_state(GenParams p, GenBuffers b, double rho_bar)
 }
 
 // One VPL per stratum: midpoint target, inverse CDF, placement, eq. (2).
+template <int S>
 __global__ __launch_bounds__(kGenBlock) void k_strata(DevScene s, DevLight dl, GenParams p, GenBuffers b, DevVpls v)
 {
     VPLG_LDS_STACK(stk);
-    int kk = blockIdx.x * blockDim.x + threadIdx.x;
-    if (kk >= b.state->k_eff || (b.state->flags & 2)) return;
-    long long Q = b.state->q_total;
-    long long ne = b.state->n_eligible;
-    long long K = p.k_near;
-    // stratum bounds B_k = floor(k f(N) / K) (k Q fits: (2K + 1) Q does)
-    const long long Bk = ((long long)kk * Q) / K, Bk1 = ((long long)(kk + 1) * Q) / K;
-    long long u;
-    if (p.jitter) {
-        const long long len = Bk1 - Bk;
-        long long off = 0;
-        if (len > 0) {
-            off = (long long)floor(halton(5, kk + 1) * (double)len);
-            if (off > len - 1) off = len - 1;
+    __shared__ double s_term[kGenBlock];
+    // S lanes per stratum (one quad-light sample each), else one
+    const int kk = blockIdx.x * (kGenBlock / S) + threadIdx.x / S;
+    const bool live = kk < b.state->k_eff && !(b.state->flags & 2);
+    const bool lead = threadIdx.x % S == 0;
+    long long Q = 0, ne = 0, Bk = 0, Bk1 = 0;
+    const long long K = p.k_near;
+    d3 y = mk(0.0, 0.0, 0.0), nk = mk(0.0, 0.0, 1.0);
+    int t = 0;
+    if (live) {
+        Q = b.state->q_total;
+        ne = b.state->n_eligible;
+        // stratum bounds B_k = floor(k f(N) / K) (k Q fits: (2K + 1) Q does)
+        Bk = ((long long)kk * Q) / K;
+        Bk1 = ((long long)(kk + 1) * Q) / K;
+        long long u;
+        if (p.jitter) {
+            const long long len = Bk1 - Bk;
+            long long off = 0;
+            if (len > 0) {
+                off = (long long)floor(halton(5, kk + 1) * (double)len);
+                if (off > len - 1) off = len - 1;
+            }
+            u = Bk + off;
+        } else {
+            u = ((2 * (long long)kk + 1) * Q) / (2 * K);
         }
-        u = Bk + off;
-    } else {
-        u = ((2 * (long long)kk + 1) * Q) / (2 * K);
+        long long lo = 0, hi = ne;  // smallest j with F[j] > u
+        while (lo < hi) {
+            long long mid = (lo + hi) >> 1;
+            if (b.F[mid] > u) hi = mid; else lo = mid + 1;
+        }
+        if (lead) b.strata[kk] = (int32_t)lo;
+        int g = b.sorted[lo];
+        t = tri_of_patch(b.patch_off, s.n_tris, g);
+        int n = b.level[t];
+        int a, bb, down;
+        local_to_ab(n, (int)(g - b.patch_off[t]), &a, &bb, &down);
+        d3 A = vA(s, t);
+        d3 e1 = sub(vB(s, t), A), e2 = sub(vC(s, t), A);
+        d3 P[3];
+        patch_verts(A, e1, e2, n, a, bb, down, P);
+        double r1 = halton(2, kk + 1), r2 = halton(3, kk + 1);
+        double sq = sqrt(r1);
+        double w0 = 1.0 - sq, w1 = sq * (1.0 - r2), w2 = sq * r2;
+        y = mk(w0 * P[0].x + w1 * P[1].x + w2 * P[2].x, w0 * P[0].y + w1 * P[1].y + w2 * P[2].y,
+               w0 * P[0].z + w1 * P[1].z + w2 * P[2].z);
+        nk = norm(cross(e1, e2));
     }
-    long long lo = 0, hi = ne;  // smallest j with F[j] > u
-    while (lo < hi) {
-        long long mid = (lo + hi) >> 1;
-        if (b.F[mid] > u) hi = mid; else lo = mid + 1;
-    }
-    b.strata[kk] = (int32_t)lo;
-    int g = b.sorted[lo];
-    int t = tri_of_patch(b.patch_off, s.n_tris, g);
-    int n = b.level[t];
-    int a, bb, down;
-    local_to_ab(n, (int)(g - b.patch_off[t]), &a, &bb, &down);
-    d3 A = vA(s, t);
-    d3 e1 = sub(vB(s, t), A), e2 = sub(vC(s, t), A);
-    d3 P[3];
-    patch_verts(A, e1, e2, n, a, bb, down, P);
-    double r1 = halton(2, kk + 1), r2 = halton(3, kk + 1);
-    double sq = sqrt(r1);
-    double w0 = 1.0 - sq, w1 = sq * (1.0 - r2), w2 = sq * r2;
-    d3 y = mk(w0 * P[0].x + w1 * P[1].x + w2 * P[2].x, w0 * P[0].y + w1 * P[1].y + w2 * P[2].y,
-              w0 * P[0].z + w1 * P[1].z + w2 * P[2].z);
-    d3 nk = norm(cross(e1, e2));
     Light64 L = light64(dl);
+    // eq. (2)'s light factor at the VPL's point (every lane of the block takes part)
+    const double gsum = p.brightness ? 0.0 : light_factor_group<S>(s, L, y, nk, t, p.t_eps, live, s_term, stk);
+    if (!live || !lead) return;
     v.px[kk] = (float)y.x; v.py[kk] = (float)y.y; v.pz[kk] = (float)y.z;
     v.nx[kk] = (float)nk.x; v.ny[kk] = (float)nk.y; v.nz[kk] = (float)nk.z;
     float* outs[3] = {v.ir, v.ig, v.ib};
     const double unit = (p.patch_h * p.patch_h) * 0x1p-24;
     if (!p.brightness) {
         double D = ((double)Q * unit) / (double)K;
-        double gsum = light_factor64(s, L, y, nk, t, p.t_eps, stk);
         for (int c = 0; c < 3; ++c) {
             double E = L.power[c] * gsum;
             double phi = ((double)s.albedo[3 * t + c] * E) * D;
@@ -996,10 +1059,22 @@ hipError_t launch_generate(const DevScene& sc, const DevLight& L, const CamBasis
     bb.F = b.scan_out + 1;
     bb.patch_g = reinterpret_cast<double*>(b.sortbuf);
     if (p.brightness && p.k_near > 0 && NP > 0)
-        hipLaunchKernelGGL(k_patch_light, dim3(nblocks(NP, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb);
+    {
+        // quad light: one lane per light sample (16 per patch)
+        if (L.kind == 1)
+            hipLaunchKernelGGL(k_patch_light<16>, dim3(nblocks(NP * 16, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb);
+        else
+            hipLaunchKernelGGL(k_patch_light<1>, dim3(nblocks(NP, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb);
+    }
     hipLaunchKernelGGL(k_strata_state, dim3(1), dim3(1), 0, s, p, bb, sc.rho_bar);
-    if (p.k_near > 0)
-        hipLaunchKernelGGL(k_strata, dim3(nblocks(p.k_near, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb, v);
+    if (p.k_near > 0) {
+        // quad light and eq. (2) at the VPL's point: one lane per light sample
+        if (L.kind == 1 && !p.brightness)
+            hipLaunchKernelGGL(k_strata<16>, dim3(nblocks((long long)p.k_near * 16, kGenBlock)), dim3(kGenBlock), 0, s,
+                               sc, L, p, bb, v);
+        else
+            hipLaunchKernelGGL(k_strata<1>, dim3(nblocks(p.k_near, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb, v);
+    }
     // the walk: batches of growing size until the far target is met or
     // max_paths is reached (batches after that exit at once)
     hipLaunchKernelGGL(k_walk_begin, dim3(1), dim3(1), 0, s, bb);
