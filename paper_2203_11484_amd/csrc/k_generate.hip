@@ -214,9 +214,8 @@ __device__ __forceinline__ bool tri64(const DevScene& s, int t, d3 o, d3 d, doub
 constexpr int kStack64 = kStack + 2;
 // The FP64 traversals keep their stacks in LDS, [entry][thread] for kGenBlock
 // threads (one per lane: entries of a lane are kGenBlock words apart, so the
-// lanes of a wave hit distinct banks).  Private arrays would live in scratch,
-// and the waves that may hold scratch at once are capped: a launch of many
-// traversing waves would run a few at a time.
+// lanes of a wave hit distinct banks).  A private array indexed at run time
+// would live in scratch memory, with a memory round trip per push and pop.
 constexpr int kGenBlock = 64;
 struct LdsStack {
     int* base;  // &stack[0][thread]
