@@ -346,9 +346,18 @@ def main():
     gp = vplg.make_gather_params(prm)
     gp.tile_vpl = args.tile_vpl
 
+    # the G-buffer does not depend on the VPLs: it renders on a second stream (default priority) while
+    # the generation runs on the first, and the gather waits for both
+    side = torch.cuda.Stream()
+    go, gb_done = torch.cuda.Event(), torch.cuda.Event()
+
     def step(ev=None):
-        vplg.gbuffer_render(ctx, sid, cam, gb, stream)
+        go.record(stream)
+        side.wait_event(go)
+        vplg.gbuffer_render(ctx, sid, cam, gb, side)
+        gb_done.record(side)
         vplg.vpls_regenerate(ctx, vid, cam, prm, stream)
+        stream.wait_event(gb_done)
         if ev:
             ev[0].record(stream)
         vplg.gather(ctx, sid, vid, gb, rad, gp, stream)
