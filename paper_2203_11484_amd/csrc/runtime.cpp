@@ -817,6 +817,8 @@ static uint32_t shape_bucket(int width, int height, int n_vpls)
 
 int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls, bool batched)
 {
+    // a server thread resolves tile shapes while the caller may autotune
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     auto it = ctx->tuned.find(shape_bucket(width, height, n_vpls));
     if (it != ctx->tuned.end()) return it->second;
     if (batched) return 8;
@@ -1091,7 +1093,10 @@ int vplg_autotune(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, cons
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    ctx->tuned[shape_bucket(gb->width, gb->height, n_vpls)] = best;
+    {
+        std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+        ctx->tuned[shape_bucket(gb->width, gb->height, n_vpls)] = best;
+    }
     *best_tile_vpl = best;
     return VPLG_OK;
 }
@@ -1109,7 +1114,10 @@ int vplg_autotune_save(vplg_context* ctx, const char* path)
     FILE* f = std::fopen(path, "w");
     if (!f) return fail(VPLG_EINVAL, "cannot write %s", path);
     std::fprintf(f, "vplg-autotune 1\n");
-    for (auto& kv : ctx->tuned) std::fprintf(f, "%u %u %d\n", kv.first >> 8, kv.first & 0xff, kv.second);
+    {
+        std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+        for (auto& kv : ctx->tuned) std::fprintf(f, "%u %u %d\n", kv.first >> 8, kv.first & 0xff, kv.second);
+    }
     std::fclose(f);
     return VPLG_OK;
 }
@@ -1135,6 +1143,7 @@ int vplg_autotune_load(vplg_context* ctx, const char* path)
         t[(px << 8) | nv] = w;
     }
     std::fclose(f);
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     for (auto& kv : t) ctx->tuned[kv.first] = kv.second;
     return VPLG_OK;
 }
