@@ -230,6 +230,7 @@ int vplg_context_destroy(vplg_context* ctx)
 int vplg_context_usage(vplg_context* ctx, uint64_t* used, uint64_t* budget)
 {
     if (!ctx) return fail(VPLG_EINVAL, "null context");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     if (used) *used = ctx->used;
     if (budget) *budget = ctx->budget;
     return VPLG_OK;
@@ -716,6 +717,7 @@ int vplg_vpls_upload(vplg_context* ctx, const float* pos, const float* nrm, cons
         release_set(ctx, v);
         return fail(VPLG_EHIP, "VPL upload failed: %s", hipGetErrorString(e));
     }
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     uint64_t id = ctx->next_id++;
     ctx->sets[id] = v;
     *vplset_id = id;
@@ -792,6 +794,7 @@ int vplg_vplset_release(vplg_context* ctx, uint64_t vplset_id)
     VplSetObj* v = find_set(ctx, vplset_id);
     if (!v) return fail(VPLG_ENOTFOUND, "unknown VPL set %llu", (unsigned long long)vplset_id);
     HIPCHK(hipDeviceSynchronize());
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     release_set(ctx, v);
     ctx->sets.erase(vplset_id);
     return VPLG_OK;
