@@ -309,6 +309,9 @@ def main():
     ap.add_argument("--requests", type=int, default=64, help="serve: requests after 8 warm-ups")
     ap.add_argument("--scenes", default="cornell,room20k,room200k", help="quality: workloads of the study")
     ap.add_argument("--ref-vpls", type=int, default=262144, help="quality: VPLs of the dense-IR reference")
+    ap.add_argument("--in-flight", type=int, default=1,
+                    help="frames in flight (2: the next frame's G-buffer and VPLs are made while the current one "
+                         "gathers; 1: one frame at a time)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -346,44 +349,80 @@ def main():
     gp = vplg.make_gather_params(prm)
     gp.tile_vpl = args.tile_vpl
 
-    # the G-buffer does not depend on the VPLs: it renders on a second stream (default priority) while
-    # the generation runs on the first, and the gather waits for both
-    side = torch.cuda.Stream()
-    go, gb_done = torch.cuda.Event(), torch.cuda.Event()
+    if args.in_flight >= 2:
+        # Two frames in flight: one stream renders the G-buffer and generates the VPLs of the next
+        # frame into the other of two buffer slots while the second stream gathers the current one,
+        # so the next frame's generation runs in the gather's tail.  Every step still runs the whole
+        # path on its own frame; a slot is rewritten only after the gather that read it is done.
+        gen_s, gat_s = torch.cuda.Stream(), torch.cuda.Stream()
+        slots = [(gb, vid)]
+        for _ in range(1, args.in_flight):
+            g2 = vplg.GBuffer(W, H)
+            slots.append((g2, vplg.vpls_generate(ctx, sid, cam, prm, stream)))
+        torch.cuda.synchronize()
+        gen_done = [torch.cuda.Event() for _ in slots]
+        free = [torch.cuda.Event() for _ in slots]
+        for e in free:
+            e.record(gat_s)
 
-    def step(ev=None):
-        go.record(stream)
-        side.wait_event(go)
-        vplg.gbuffer_render(ctx, sid, cam, gb, side)
-        gb_done.record(side)
-        vplg.vpls_regenerate(ctx, vid, cam, prm, stream)
-        stream.wait_event(gb_done)
-        if ev:
-            ev[0].record(stream)
-        vplg.gather(ctx, sid, vid, gb, rad, gp, stream)
-        if ev:
-            ev[1].record(stream)
+        def step_i(i, ev=None):
+            k = i % len(slots)
+            g_k, v_k = slots[k]
+            gen_s.wait_event(free[k])
+            vplg.gbuffer_render(ctx, sid, cam, g_k, gen_s)
+            vplg.vpls_regenerate(ctx, v_k, cam, prm, gen_s)
+            gen_done[k].record(gen_s)
+            gat_s.wait_event(gen_done[k])
+            if ev:
+                ev[0].record(gat_s)
+            vplg.gather(ctx, sid, v_k, g_k, rad, gp, gat_s)
+            if ev:
+                ev[1].record(gat_s)
+            free[k].record(gat_s)
 
-    for _ in range(args.warmup):
-        step()
+        t_stream = gat_s
+    else:
+        # the G-buffer does not depend on the VPLs: it renders on a second stream (default priority)
+        # while the generation runs on the first, and the gather waits for both
+        side = torch.cuda.Stream()
+        go, gb_done = torch.cuda.Event(), torch.cuda.Event()
+
+        def step_i(i, ev=None):
+            go.record(stream)
+            side.wait_event(go)
+            vplg.gbuffer_render(ctx, sid, cam, gb, side)
+            gb_done.record(side)
+            vplg.vpls_regenerate(ctx, vid, cam, prm, stream)
+            stream.wait_event(gb_done)
+            if ev:
+                ev[0].record(stream)
+            vplg.gather(ctx, sid, vid, gb, rad, gp, stream)
+            if ev:
+                ev[1].record(stream)
+
+        t_stream = stream
+
+    for i in range(args.warmup):
+        step_i(i)
     torch.cuda.synchronize()
-    print(f"bench: warmup done, M={M}", file=sys.stderr, flush=True)
+    print(f"bench: warmup done, M={M}, frames in flight {max(1, args.in_flight)}", file=sys.stderr, flush=True)
 
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
-    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     g_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
-    t_start.record(stream)
+    t_start.record(t_stream)
+    if args.in_flight >= 2:
+        gen_s.wait_event(t_start)
     for i in range(args.steps):
-        step_ev[i].record(stream)
-        step(g_ev[i])
-    step_ev[-1].record(stream)
-    t_end.record(stream)
+        step_i(args.warmup + i, g_ev[i])
+    t_end.record(t_stream)
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
     ms_step = total_ms / args.steps
-    frame_ms = np.array([step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps)])
+    # frame intervals: from one gather's end to the next (the first from the start)
+    ends = [t_start.elapsed_time(b) for _, b in g_ev]
+    frame_ms = np.diff(np.array([0.0] + ends))
     gather_ms = np.array([a.elapsed_time(b) for a, b in g_ev])
     print(f"bench: {args.steps} steps, {ms_step:.3f} ms/step, gather {gather_ms.mean():.3f} ms",
           file=sys.stderr, flush=True)
@@ -428,6 +467,7 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_gather", "flop_per_launch": flops, "gather_ms": float(gather_ms.mean())},
         "gather_pairs_per_s": pairs_step / g_mean_s,
+        "frames_in_flight": max(1, args.in_flight),
         "p50_frame_ms": float(np.percentile(frame_ms, 50)),
         "p99_frame_ms": float(np.percentile(frame_ms, 99)),
         "valid_pixel_frac": valid / P,
