@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "runtime_internal.h"
+#include "server_pool.h"
 
 using namespace vplg;
 using namespace vplg::rt;
@@ -34,20 +35,6 @@ int64_t now_ns()
     return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
         .count();
 }
-
-struct PoolSet {
-    VplSetObj* v = nullptr;
-    uint64_t scene = 0;
-    int k = 0, n = 0;
-    double h = 0.0;
-    bool busy = false;
-};
-
-struct PoolGb {
-    void* mem = nullptr;
-    size_t bytes = 0;
-    bool busy = false;
-};
 
 struct ReqObj {
     uint64_t ticket = 0;
@@ -72,8 +59,8 @@ struct vplg_server {
     std::deque<ReqObj*> queue;
     std::vector<ReqObj*> running;
     std::map<uint64_t, ReqObj*> reqs;
-    std::vector<PoolSet> sets;
-    std::vector<PoolGb> gbufs;
+    std::vector<pool::Set> sets;  // Set::v is a VplSetObj*
+    std::vector<pool::Gb> gbufs;
     std::vector<hipStream_t> streams;
     int next_stream = 0;
     uint64_t next_ticket = 1;
@@ -84,53 +71,25 @@ struct vplg_server {
 
 namespace {
 
-// Free idle pool entries until `need` more bytes fit the budget.
-bool make_room(vplg_server* s, uint64_t need)
-{
-    const uint64_t budget = s->prm.hbm_budget_bytes;
-    if (s->used + need <= budget) return true;
-    uint64_t idle = 0;
-    for (auto& p : s->sets)
-        if (p.v && !p.busy) idle += p.v->bytes;
-    for (auto& g : s->gbufs)
-        if (g.mem && !g.busy) idle += g.bytes;
-    if (s->used - idle + need > budget) return false;
-    for (auto& p : s->sets)
-        if (p.v && !p.busy && s->used + need > budget) {
-            s->used -= p.v->bytes;
-            release_set(s->ctx, p.v);
-            p.v = nullptr;
-        }
-    for (auto& g : s->gbufs)
-        if (g.mem && !g.busy && s->used + need > budget) {
-            (void)hipFree(g.mem);
-            s->used -= g.bytes;
-            g.mem = nullptr;
-        }
-    return s->used + need <= budget;
-}
-
 // Reserve pooled buffers for the queue head; false if they do not fit yet.
+// The entries the request reuses are held before anything is freed: eviction
+// only ever frees other idle entries.
 bool reserve(vplg_server* s, ReqObj* q)
 {
-    int si = -1, gi = -1;
-    for (int i = 0; i < (int)s->sets.size(); ++i) {
-        PoolSet& p = s->sets[i];
-        if (p.v && !p.busy && p.scene == q->r.scene_id && p.k == q->r.gen.k_near && p.n == q->r.gen.n_far &&
-            p.h == q->r.gen.patch_h) {
-            si = i;
-            break;
-        }
+    const pool::Want w{q->r.scene_id, q->r.gen.k_near, q->r.gen.n_far, q->r.gen.patch_h, q->gb_bytes, q->set_bytes};
+    const pool::Plan p = pool::plan(s->sets, s->gbufs, s->used, s->prm.hbm_budget_bytes, w);
+    if (!p.fits) return false;
+    for (int i : p.evict_sets) {
+        release_set(s->ctx, (VplSetObj*)s->sets[i].v);
+        s->used -= s->sets[i].bytes;
+        s->sets[i].v = nullptr;
     }
-    for (int i = 0; i < (int)s->gbufs.size(); ++i) {
-        PoolGb& g = s->gbufs[i];
-        if (g.mem && !g.busy && g.bytes >= q->gb_bytes && g.bytes <= 2 * q->gb_bytes) {
-            gi = i;
-            break;
-        }
+    for (int i : p.evict_gbs) {
+        (void)hipFree(s->gbufs[i].mem);
+        s->used -= s->gbufs[i].bytes;
+        s->gbufs[i].mem = nullptr;
     }
-    uint64_t need = (si < 0 ? q->set_bytes : 0) + (gi < 0 ? q->gb_bytes : 0);
-    if (need && !make_room(s, need)) return false;
+    int si = p.set, gi = p.gb;
     if (si < 0) {
         SceneObj* so = find_scene(s->ctx, q->r.scene_id);
         PatchIndex* pi = nullptr;
@@ -140,33 +99,32 @@ bool reserve(vplg_server* s, ReqObj* q)
             q->error = so ? VPLG_ENOMEM : VPLG_ENOTFOUND;
             return true;  // admitted as failed
         }
-        PoolSet p;
-        p.v = v;
-        p.scene = q->r.scene_id;
-        p.k = q->r.gen.k_near;
-        p.n = q->r.gen.n_far;
-        p.h = q->r.gen.patch_h;
-        s->used += v->bytes;
-        si = -1;
+        pool::Set e;
+        e.v = v;
+        e.bytes = v->bytes;
+        e.scene = q->r.scene_id;
+        e.k = q->r.gen.k_near;
+        e.n = q->r.gen.n_far;
+        e.h = q->r.gen.patch_h;
+        s->used += e.bytes;
         for (int i = 0; i < (int)s->sets.size(); ++i)
             if (!s->sets[i].v) si = i;
         if (si < 0) {
-            s->sets.push_back(p);
+            s->sets.push_back(e);
             si = (int)s->sets.size() - 1;
         } else {
-            s->sets[si] = p;
+            s->sets[si] = e;
         }
     }
     if (gi < 0) {
-        PoolGb g;
+        pool::Gb g;
         g.bytes = q->gb_bytes;
         if (hipMalloc(&g.mem, g.bytes) != hipSuccess) {
             (void)hipGetLastError();
             q->error = VPLG_ENOMEM;
-            return true;
+            return true;  // admitted as failed (a new set stays in the pool, idle)
         }
         s->used += g.bytes;
-        gi = -1;
         for (int i = 0; i < (int)s->gbufs.size(); ++i)
             if (!s->gbufs[i].mem) gi = i;
         if (gi < 0) {
@@ -198,6 +156,8 @@ int launch(vplg_server* s, ReqObj* q)
     const int W = r.camera.width, H = r.camera.height;
     const size_t P = (size_t)W * H;
     char* base = (char*)s->gbufs[q->gb_idx].mem;
+    VplSetObj* v = (VplSetObj*)s->sets[q->set_idx].v;
+    if (!base || !v) return fail(VPLG_EHIP, "server pool entry without memory");  // never launch on it
     vplg_gbuffer gb;
     for (int c = 0; c < 3; ++c) {
         gb.pos[c] = (float*)(base + (0 + c) * P * 4);
@@ -212,7 +172,6 @@ int launch(vplg_server* s, ReqObj* q)
     hipStream_t st = s->streams[q->stream_idx];
     SceneObj* so = find_scene(s->ctx, r.scene_id);
     if (!so) return VPLG_ENOTFOUND;
-    VplSetObj* v = s->sets[q->set_idx].v;
     int rc;
     if ((rc = render_gbuffer(so, &r.camera, &gb, st))) return rc;
     if ((rc = launch_genset(so, v, &r.camera, &r.gen, st))) return rc;
@@ -444,7 +403,7 @@ int vplg_server_stop(vplg_server* s)
     (void)hipSetDevice(s->ctx->device);
     for (auto st : s->streams) (void)hipStreamSynchronize(st);
     for (auto& p : s->sets)
-        if (p.v) release_set(s->ctx, p.v);
+        if (p.v) release_set(s->ctx, (VplSetObj*)p.v);
     for (auto& g : s->gbufs)
         if (g.mem) (void)hipFree(g.mem);
     for (auto& kv : s->reqs) {
