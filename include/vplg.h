@@ -243,15 +243,19 @@ typedef struct {
 /* radiance[c][p] = (albedo_p[c] / pi) * sum_k I_k[c] * min(C, max(0, n_p.d)
  * max(0, -n_k.d) / |d|^4) * V(x_p, y_k), d = y_k - x_p, for every pixel of
  * gb; pixels with tri < 0 get 0.  radiance: three caller-owned device planes
- * of width * height float32.  Float32 arithmetic, per-tile partial sums
- * added in a fixed order (deterministic).
+ * of width * height float32.  Float32 arithmetic, partial sums added in a
+ * fixed order per pixel (deterministic: a pixel's value depends only on its
+ * inputs and tile_vpl).
  * The launch is a resident grid whose workgroups claim 8 x 8 tiles from a
- * device word that the library keeps for `stream` (allocated on the
- * stream's first gather, reset by a kernel before each launch).  Gathers on
- * one stream are ordered and may share it; gathers on different streams
- * run concurrently.  A gather captured into a HIP graph keeps the word of
- * the stream it was captured on: do not replay it concurrently with other
- * gathers on that stream or with another replay. */
+ * counter in work memory that the library keeps for `stream` (about 6 MB,
+ * allocated on the stream's first gather, outside the context's budget;
+ * the counter is reset by a kernel before each launch).  The last tiles are
+ * claimed in four parts each, whose sums a second kernel on the stream adds
+ * up.  Gathers on one stream are ordered and may share the work memory;
+ * gathers on different streams run concurrently.  A gather captured into a
+ * HIP graph keeps the work memory of the stream it was captured on: do not
+ * replay it concurrently with other gathers on that stream or with another
+ * replay. */
 int vplg_gather(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                 float* const radiance[3], const vplg_gather_params* p, void* stream);
 

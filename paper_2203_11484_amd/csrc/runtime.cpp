@@ -222,7 +222,10 @@ int vplg_context_destroy(vplg_context* ctx)
     if (be.d_counter) (void)hipFree(be.d_counter);
     if (be.h_tab) (void)hipHostFree(be.h_tab);
     if (be.h_views) (void)hipHostFree(be.h_views);
-    for (auto& kv : ctx->stream_counters) (void)hipFree(kv.second);
+    for (auto& kv : ctx->stream_work) {
+        (void)hipFree(kv.second.counter);
+        (void)hipFree(kv.second.part);
+    }
     delete ctx;
     return VPLG_OK;
 }
@@ -859,6 +862,9 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
     a->g_clamp = p->g_clamp;
     a->t_eps = p->t_eps;
     a->counters = nullptr;
+    a->split_cap = 0;
+    a->split_full = a->split_count = 0;
+    a->split_part = nullptr;
     // tile_vpl: waves (VPL slices) per 8 x 8 tile; 0 = the autotuned choice, else the tile-count rule
     int w = p->tile_vpl == 0 ? tuned_waves(ctx, gb->width, gb->height, v->dev.capacity, batched) : p->tile_vpl;
     if (w < 1 || w > 16 || (w & (w - 1)))
@@ -870,16 +876,21 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
 
 int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s)
 {
-    unsigned int* counter = nullptr;
+    GatherWork wk;
     int blocks = 0;
     {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-        auto it = ctx->stream_counters.find((void*)s);
-        if (it == ctx->stream_counters.end()) {
-            HIPCHK(hipMalloc(&counter, sizeof(unsigned int)));
-            ctx->stream_counters[(void*)s] = counter;
+        auto it = ctx->stream_work.find((void*)s);
+        if (it == ctx->stream_work.end()) {
+            HIPCHK(hipMalloc(&wk.counter, sizeof(unsigned int)));
+            hipError_t e = hipMalloc(&wk.part, sizeof(float) * (size_t)kGatherSplitCap * gather_split_floats_per_tile());
+            if (e != hipSuccess) {
+                (void)hipFree(wk.counter);
+                return fail(VPLG_EHIP, "gather work memory: %s", hipGetErrorString(e));
+            }
+            ctx->stream_work[(void*)s] = wk;
         } else {
-            counter = it->second;
+            wk = it->second;
         }
         if (ctx->cus == 0) HIPCHK(hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
         const int lw = __builtin_ctz((unsigned)a.waves_per_tile);
@@ -890,7 +901,10 @@ int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t
         }
         blocks = ctx->cus * per_cu;
     }
-    HIPCHK(launch_gather(a, counted, counter, blocks, s));
+    GatherArgs b = a;
+    b.split_cap = kGatherSplitCap;
+    b.split_part = wk.part;
+    HIPCHK(launch_gather(b, counted, wk.counter, blocks, s));
     return VPLG_OK;
 }
 

@@ -82,6 +82,18 @@ struct BatchEngine {
 }  // namespace rt
 }  // namespace vplg
 
+namespace vplg {
+namespace rt {
+// Per-stream work memory of the single-view gather: its tile counter and the
+// round-group sums of up to kGatherSplitCap split tiles.
+constexpr int kGatherSplitCap = 2048;
+struct GatherWork {
+    unsigned int* counter = nullptr;
+    float* part = nullptr;
+};
+}  // namespace rt
+}  // namespace vplg
+
 struct vplg_context {
     int device = 0;
     uint64_t budget = 0, used = 0;
@@ -90,9 +102,9 @@ struct vplg_context {
     std::map<uint64_t, vplg::rt::VplSetObj*> sets;
     vplg::rt::BatchEngine batch;
     std::map<uint32_t, int> tuned;  // view-shape bucket -> waves per 8 x 8 tile
-    // tile counter of the persistent single-view gather, one device word per
-    // stream (launches on one stream are ordered, so they may share it)
-    std::map<void*, unsigned int*> stream_counters;
+    // work memory of the persistent single-view gather, per stream (launches
+    // on one stream are ordered, so they may share it)
+    std::map<void*, vplg::rt::GatherWork> stream_work;
     int cus = 0;                      // compute units of the device
     int gather_blocks[2][5] = {};     // [counted][log2 waves]: resident workgroups per CU, 0 = not queried
     std::recursive_mutex mu;        // budget accounting, shared with a running server thread

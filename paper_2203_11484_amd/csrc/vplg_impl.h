@@ -96,6 +96,13 @@ struct GatherArgs {
     float t_eps;
     int waves_per_tile;            // VPL slices per 8 x 8 pixel tile: 1, 2, 4, 8 or 16
     unsigned long long* counters;  // instrumented variant only
+    // single-view gather only: split_part holds [split_cap][kGroups][3][64]
+    // floats of work memory (split_cap 0: no tile is split); the launcher sets
+    // split_full (whole tiles claimed first) and split_count (tiles after it,
+    // claimed by round group)
+    int split_cap;
+    int split_full, split_count;
+    float* split_part;
 };
 
 // Work table of a batched gather: views sorted by the caller, prefix[v] =
@@ -206,6 +213,8 @@ struct GenBuffers {
 hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counter, int blocks, hipStream_t s);
 // Resident workgroups per CU of the single-view gather for `waves` waves per tile.
 hipError_t gather_occupancy(int waves, bool counted, int* blocks_per_cu);
+// Floats of split-tile work memory per tile (its round groups' sums).
+int gather_split_floats_per_tile();
 hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s);
 hipError_t launch_gather_batch(const BatchTable* tab, const GatherArgs* views, unsigned int* counter, int blocks,
                                int block_waves, hipStream_t s);
