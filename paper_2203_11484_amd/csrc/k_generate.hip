@@ -396,8 +396,11 @@ __global__ void k_classify(DevScene s, CamBasis cb, DevLight dl, GenParams p, Ge
 {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     __shared__ int s_near, s_el;
+    __shared__ unsigned long long s_base;
     if (threadIdx.x == 0) { s_near = 0; s_el = 0; }
     __syncthreads();
+    unsigned long long key = ~0ull;
+    int pos = -1;  // this patch's place among the block's eligible patches
     if (g < b.n_patches) {
         int t = tri_of_patch(b.patch_off, s.n_tris, g);
         int n = b.level[t];
@@ -412,7 +415,6 @@ __global__ void k_classify(DevScene s, CamBasis cb, DevLight dl, GenParams p, Ge
         Cam64 k = cam64(cb);
         Light64 L = light64(dl);
         uint8_t fl = 0;
-        unsigned long long key = ~0ull;
         if (!(s.flags[t] & 1) && is_near(k, c, p.d_near)) {
             fl |= 1;
             d3 nt = norm(cross(e1, e2));
@@ -427,15 +429,18 @@ __global__ void k_classify(DevScene s, CamBasis cb, DevLight dl, GenParams p, Ge
             }
         }
         b.pflags[g] = fl;
-        b.sortbuf[g] = key;
         if (fl & 1) atomicAdd(&s_near, 1);
-        if (fl & 2) atomicAdd(&s_el, 1);
+        if (fl & 2) pos = atomicAdd(&s_el, 1);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         if (s_near) atomicAdd((unsigned long long*)&b.state->n_near, (unsigned long long)s_near);
-        if (s_el) atomicAdd((unsigned long long*)&b.state->n_eligible, (unsigned long long)s_el);
+        s_base = s_el ? atomicAdd((unsigned long long*)&b.state->n_eligible, (unsigned long long)s_el) : 0ull;
     }
+    __syncthreads();
+    // eligible keys go to the front of the sort buffer, in any order: the
+    // (key, patch) pairs are unique, so their sorted order is fixed
+    if (pos >= 0) b.sortbuf[s_base + pos] = key;
 }
 
 __global__ void k_fill_u64(unsigned long long* p, long long from, long long to, unsigned long long v)
@@ -444,11 +449,26 @@ __global__ void k_fill_u64(unsigned long long* p, long long from, long long to, 
     if (i < to) p[i] = v;
 }
 
+constexpr int kLocal = 2048;  // elements per workgroup in the LDS stages
+
+// The sort runs on the front of the buffer that holds the eligible keys: the
+// next power of two >= max(n_eligible, kLocal) elements (the rest are all-ones
+// keys that stay in place).  Passes of a larger level, and elements past it,
+// have nothing to do.
+__device__ __forceinline__ long long sort_extent(const GenState* st)
+{
+    const long long ne = st->n_eligible;
+    long long m = kLocal;
+    while (m < ne) m <<= 1;
+    return m;
+}
+
 // Bitonic sort (ascending) of a power-of-two array of unique 64-bit keys.
-__global__ void k_bitonic_global(unsigned long long* a, long long n, long long j, long long k)
+__global__ void k_bitonic_global(unsigned long long* a, long long n, long long j, long long k, const GenState* st)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const long long m = sort_extent(st);
+    if (i >= n || i >= m || k > m) return;
     long long l = i ^ j;
     if (l > i) {
         unsigned long long x = a[i], y = a[l];
@@ -457,14 +477,14 @@ __global__ void k_bitonic_global(unsigned long long* a, long long n, long long j
     }
 }
 
-constexpr int kLocal = 2048;  // elements per workgroup in the LDS stages
-
 // All stages j < kLocal of level k (k <= kLocal: the whole local sort up to k).
 __global__ __launch_bounds__(1024) void k_bitonic_local(unsigned long long* a, long long n, long long k_from,
-                                                        long long k_to, long long j_from)
+                                                        long long k_to, long long j_from, const GenState* st)
 {
     __shared__ unsigned long long s[kLocal];
     long long base = (long long)blockIdx.x * kLocal;
+    const long long m = sort_extent(st);
+    if (base >= m || k_from > m) return;  // uniform over the workgroup
     for (int i = threadIdx.x; i < kLocal; i += blockDim.x) s[i] = a[base + i];
     __syncthreads();
     for (long long k = k_from; k <= k_to; k <<= 1) {
@@ -1038,15 +1058,20 @@ hipError_t launch_generate(const DevScene& sc, const DevLight& L, const CamBasis
     long long n2 = kLocal;
     while (n2 < NP) n2 <<= 1;
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, b, NP);
+    hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(n2, GB)), dim3(GB), 0, s, b.sortbuf, 0ll, n2, ~0ull);
     if (NP > 0) hipLaunchKernelGGL(k_classify, dim3(nblocks(NP, GB)), dim3(GB), 0, s, sc, cam, L, p, b);
-    if (n2 > NP) hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(n2 - NP, GB)), dim3(GB), 0, s, b.sortbuf, NP, n2, ~0ull);
-    // bitonic sort: LDS stages for j < kLocal, global passes above
+    // bitonic sort: LDS stages for j < kLocal, global passes above; the
+    // network is launched for every patch, and its passes skip what lies past
+    // the eligible keys' power of two (known on the device only)
     unsigned lb = (unsigned)(n2 / kLocal);
-    hipLaunchKernelGGL(k_bitonic_local, dim3(lb), dim3(1024), 0, s, b.sortbuf, n2, 2ll, (long long)kLocal, 1ll);
+    hipLaunchKernelGGL(k_bitonic_local, dim3(lb), dim3(1024), 0, s, b.sortbuf, n2, 2ll, (long long)kLocal, 1ll,
+                       (const GenState*)b.state);
     for (long long k = 2ll * kLocal; k <= n2; k <<= 1) {
         for (long long j = k >> 1; j >= kLocal; j >>= 1)
-            hipLaunchKernelGGL(k_bitonic_global, dim3(nblocks(n2, GB)), dim3(GB), 0, s, b.sortbuf, n2, j, k);
-        hipLaunchKernelGGL(k_bitonic_local, dim3(lb), dim3(1024), 0, s, b.sortbuf, n2, k, k, (long long)(kLocal / 2));
+            hipLaunchKernelGGL(k_bitonic_global, dim3(nblocks(n2, GB)), dim3(GB), 0, s, b.sortbuf, n2, j, k,
+                               (const GenState*)b.state);
+        hipLaunchKernelGGL(k_bitonic_local, dim3(lb), dim3(1024), 0, s, b.sortbuf, n2, k, k, (long long)(kLocal / 2),
+                           (const GenState*)b.state);
     }
     // fixed-point areas -> inclusive prefix F
     if (NP > 0) {

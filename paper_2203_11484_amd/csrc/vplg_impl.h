@@ -181,7 +181,7 @@ struct GenBuffers {
     int32_t* level;         // [T] refinement level of each triangle
     long long* patch_off;   // [T + 1]
     uint8_t* pflags;        // [n_patches]
-    unsigned long long* sortbuf;  // [pow2 >= n_patches] (key << 32 | patch)
+    unsigned long long* sortbuf;  // [pow2 >= n_patches] (key << 32 | patch): eligible patches first, then all-ones
     double* patch_g;        // = sortbuf once the order is extracted: eq. (2)'s light factor per sorted patch
     int32_t* sorted;        // [n_patches]
     uint32_t* keys;         // [n_patches]
