@@ -648,13 +648,13 @@ __global__ void k_strata_state(GenParams p, GenBuffers b, double rho_bar)
 }
 
 // One VPL per stratum: midpoint target, inverse CDF, placement, eq. (2).
+// (block `blk` of the strata's blocks; every lane of the block must call it)
 template <int S>
-__global__ __launch_bounds__(kGenBlock) void k_strata(DevScene s, DevLight dl, GenParams p, GenBuffers b, DevVpls v)
+__device__ __forceinline__ void strata_block(const DevScene& s, const DevLight& dl, const GenParams& p, const GenBuffers& b,
+                             const DevVpls& v, int blk, LdsStack stk, double* s_term)
 {
-    VPLG_LDS_STACK(stk);
-    __shared__ double s_term[kGenBlock];
     // S lanes per stratum (one quad-light sample each), else one
-    const int kk = blockIdx.x * (kGenBlock / S) + threadIdx.x / S;
+    const int kk = blk * (kGenBlock / S) + threadIdx.x / S;
     const bool live = kk < b.state->k_eff && !(b.state->flags & 2);
     const bool lead = threadIdx.x % S == 0;
     long long Q = 0, ne = 0, Bk = 0, Bk1 = 0;
@@ -743,11 +743,11 @@ __global__ __launch_bounds__(kGenBlock) void k_strata(DevScene s, DevLight dl, G
 }
 
 // One thread per walk path of the batch [start + 1, start + batch].
-__global__ __launch_bounds__(kGenBlock) void k_walk(DevScene s, DevLight dl, GenParams p, GenBuffers b, long long start,
-                                                    int nb)
+// (block `blk` of the batch's blocks; no barrier inside)
+__device__ __forceinline__ void walk_block(const DevScene& s, const DevLight& dl, const GenParams& p, const GenBuffers& b,
+                           long long start, int nb, int blk, LdsStack stk)
 {
-    VPLG_LDS_STACK(stk);
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = blk * blockDim.x + threadIdx.x;
     if (i >= nb || b.state->walk_done) return;
     long long path = start + i + 1;
     b.w_count[i] = 0;
@@ -820,6 +820,30 @@ __global__ __launch_bounds__(kGenBlock) void k_walk(DevScene s, DevLight dl, Gen
         skip_emit = false;
     }
     b.w_count[i] = cnt | (discard_mask << 8);
+}
+
+__global__ __launch_bounds__(kGenBlock) void k_walk(DevScene s, DevLight dl, GenParams p, GenBuffers b, long long start,
+                                                    int nb)
+{
+    VPLG_LDS_STACK(stk);
+    walk_block(s, dl, p, b, start, nb, blockIdx.x, stk);
+}
+
+// The near strata and the walk's first batch in one launch.  Both are
+// latency-bound (few waves, long dependent FP64 traversals) and independent
+// once k_strata_state has run (disjoint VPL ranges; the state they read is
+// final), so they share the GPU instead of running one after the other:
+// blocks [0, sb) place strata, the rest walk paths [start + 1, start + nb].
+template <int S>
+__global__ __launch_bounds__(kGenBlock) void k_strata_walk(DevScene s, DevLight dl, GenParams p, GenBuffers b, DevVpls v,
+                                                           int sb, long long start, int nb)
+{
+    VPLG_LDS_STACK(stk);
+    __shared__ double s_term[kGenBlock];
+    if ((int)blockIdx.x < sb)
+        strata_block<S>(s, dl, p, b, v, blockIdx.x, stk, s_term);
+    else
+        walk_block(s, dl, p, b, start, nb, blockIdx.x - sb, stk);
 }
 
 // One workgroup per batch: keep deposits in (path, bounce) order up to the
@@ -1091,22 +1115,25 @@ hipError_t launch_generate(const DevScene& sc, const DevLight& L, const CamBasis
             hipLaunchKernelGGL(k_patch_light<1>, dim3(nblocks(NP, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb);
     }
     hipLaunchKernelGGL(k_strata_state, dim3(1), dim3(1), 0, s, p, bb, sc.rho_bar);
-    if (p.k_near > 0) {
-        // quad light and eq. (2) at the VPL's point: one lane per light sample
-        if (L.kind == 1 && !p.brightness)
-            hipLaunchKernelGGL(k_strata<16>, dim3(nblocks((long long)p.k_near * 16, kGenBlock)), dim3(kGenBlock), 0, s,
-                               sc, L, p, bb, v);
-        else
-            hipLaunchKernelGGL(k_strata<1>, dim3(nblocks(p.k_near, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb, v);
-    }
-    // the walk: batches of growing size until the far target is met or
-    // max_paths is reached (batches after that exit at once)
+    // the walk: batches until the far target is met or max_paths is reached
+    // (batches after that exit at once)
     hipLaunchKernelGGL(k_walk_begin, dim3(1), dim3(1), 0, s, bb);
     long long start = 0;
-    // the walk is latency-bound (one serial path per thread): the first
-    // batch takes the whole capacity; deposits are kept in path order, so
-    // the batch sizes never change the result
+    // the walk is latency-bound (one serial path per thread): every batch
+    // takes the whole capacity; deposits are kept in path order, so the batch
+    // sizes never change the result.  The first batch runs in one launch with
+    // the near strata (quad light and eq. (2) at the VPL's point: one lane
+    // per light sample).
     int nb = b.batch;
+    const bool quad = L.kind == 1 && !p.brightness;
+    const int sb = p.k_near > 0 ? (int)nblocks((long long)p.k_near * (quad ? 16 : 1), kGenBlock) : 0;
+    const unsigned fused = (unsigned)(sb + nblocks(nb, kGenBlock));
+    if (quad)
+        hipLaunchKernelGGL(k_strata_walk<16>, dim3(fused), dim3(kGenBlock), 0, s, sc, L, p, bb, v, sb, start, nb);
+    else
+        hipLaunchKernelGGL(k_strata_walk<1>, dim3(fused), dim3(kGenBlock), 0, s, sc, L, p, bb, v, sb, start, nb);
+    hipLaunchKernelGGL(k_walk_collect, dim3(1), dim3(COLLECT_T), 0, s, p, bb, v, start, nb);
+    start += nb;
     while (start < p.max_paths) {
         hipLaunchKernelGGL(k_walk, dim3(nblocks(nb, kGenBlock)), dim3(kGenBlock), 0, s, sc, L, p, bb, start, nb);
         hipLaunchKernelGGL(k_walk_collect, dim3(1), dim3(COLLECT_T), 0, s, p, bb, v, start, nb);
