@@ -83,6 +83,34 @@ def test_batch_equals_per_view_and_replays(vplg, ctx):
         assert torch.equal(v["radiance"], refs[i])
 
 
+@pytest.mark.parametrize("size,tile_vpl", [((512, 512), 16), ((1024, 1024), 8)])
+def test_split_tail_equals_whole_tiles(vplg, ctx, size, tile_vpl):
+    """A lone gather of a view with at least four rounds of tiles claims its last two rounds as
+    quarter-tile round-group items (summed by a second kernel); a batch never splits.  The two must
+    agree bit for bit, since a tile's sum is fixed as chunk, round-group, wave and group order."""
+    w, h = size
+    tiles = ((w + 7) // 8) * ((h + 7) // 8)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    per_cu = 2 if tile_vpl == 16 else 4  # resident workgroups of that size (8 waves per SIMD)
+    assert tiles >= 4 * per_cu * cus, "the view must be large enough for the lone gather to split tiles"
+    sc = scenes.make_scene("cornell", width=w, height=h)
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
+    gb = vplg.GBuffer(w, h)
+    vplg.gbuffer_render(ctx, sid, sc["camera"], gb)
+    vid = vplg.vpls_generate(ctx, sid, sc["camera"], sc["params"])
+    gp = vplg.make_gather_params(sc["params"])
+    gp.tile_vpl = tile_vpl
+    lone = torch.full((3, h, w), -1.0, dtype=torch.float32, device="cuda")
+    vplg.gather(ctx, sid, vid, gb, lone, gp)
+    view = dict(scene=sid, vplset=vid, gb=gb, radiance=torch.full_like(lone, -1.0), params=gp)
+    vplg.gather_batch(ctx, [view])
+    torch.cuda.synchronize()
+    assert (lone >= 0).all() and (lone > 0).any()
+    assert torch.equal(view["radiance"], lone)
+    vplg.vplset_release(ctx, vid)
+    vplg.scene_release(ctx, sid)
+
+
 def test_untuned_tile_vpl_rule(vplg, ctx):
     """tile_vpl 0 on an untuned shape: a lone gather takes 16 waves per tile below 32 tiles per compute
     unit (bit for bit the explicit 16), a view in a batch takes 8."""
