@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdarg>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -45,7 +46,9 @@ struct SceneObj {
     std::vector<Alloc> allocs;
     uint64_t bytes = 0;
     vplg_scene_info info;
-    std::vector<PatchIndex> patches;
+    // one index per patch size; a deque, so that the index a caller holds
+    // stays in place when another thread adds one for another size
+    std::deque<PatchIndex> patches;
 };
 
 struct VplSetObj {
