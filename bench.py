@@ -70,7 +70,14 @@ def cpu_baseline(sc, target_s, seed=0):
     n = int(min(P, max(probe, probe * target_s / max(dt, 1e-6))))
     dt = run(n)
     pairs = n * g["n"]
-    return dict(value=pairs / dt, unit="pairs/s", cores=threads, kind="oracle",
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return dict(value=pairs / dt, unit="pairs/s", cores=threads, kind="oracle", cpu=model,
+                host_cpus=os.cpu_count(),
                 sample=f"{n} seeded random pixels of the {sc['camera']['width']}x{sc['camera']['height']} image x "
                        f"{g['n']} VPLs ({pairs} pairs, FP64, {dt:.1f} s)")
 
