@@ -743,12 +743,14 @@ __device__ __forceinline__ void strata_block(const DevScene& s, const DevLight& 
 }
 
 // One thread per walk path of the batch [start + 1, start + batch].
-// Paths per 64-lane block of the walk: a wave lasts as long as its slowest
-// path, and a batch has fewer waves than the GPU has SIMDs, so spreading its
-// paths over four times the waves shortens it (room20k: 0.05 ms per
-// generation; 32 lanes gain less).
+// Paths per 64-lane block of the walk.  A wave lasts as long as its slowest
+// path, so 16 paths per block (four times the waves) shorten a lone
+// generation (room20k: 0.05 ms of 0.93; Cornell: 0.01 of 0.24 ms), but under
+// the render server those extra waves share the SIMDs with the other
+// requests' gathers and the served median latency rises by about a tenth:
+// full 64-lane waves are kept.
 #ifndef VPLG_WALK_LANES
-#define VPLG_WALK_LANES 16
+#define VPLG_WALK_LANES 64
 #endif
 constexpr int kWalkLanes = VPLG_WALK_LANES;
 
