@@ -343,7 +343,9 @@ typedef struct vplg_server vplg_server;
 /* hbm_budget_bytes: device memory the server may hold for per-request
  * G-buffers and VPL sets (pooled; > 0).  max_inflight: requests admitted at
  * once (1..256).  n_streams: HIP streams the admitted requests are spread
- * over (1..16, default priority). */
+ * over (1..16, default priority).  The server's gathers claim whole tiles
+ * only (requests overlap, so no one view's tail idles the device); their
+ * radiance is the same as vplg_gather's. */
 typedef struct {
     uint64_t hbm_budget_bytes;
     int32_t max_inflight, n_streams;

@@ -874,7 +874,7 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
     return VPLG_OK;
 }
 
-int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s)
+int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s, bool split_tail)
 {
     GatherWork wk;
     int blocks = 0;
@@ -902,7 +902,7 @@ int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t
         blocks = ctx->cus * per_cu;
     }
     GatherArgs b = a;
-    b.split_cap = kGatherSplitCap;
+    b.split_cap = split_tail ? kGatherSplitCap : 0;
     b.split_part = wk.part;
     HIPCHK(launch_gather(b, counted, wk.counter, blocks, s));
     return VPLG_OK;

@@ -159,7 +159,9 @@ int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, cons
 int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffer* gb, float* const radiance[3],
                 const vplg_gather_params* p, GatherArgs* a, bool batched = false);
 // launch the persistent single-view gather of `a` on `s` (its stream's tile counter, resident grid)
-int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s);
+// split_tail = false: whole tiles only (for gathers that share the GPU with
+// others, where no one view's tail leaves it idle); the result is the same.
+int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s, bool split_tail = true);
 
 }  // namespace rt
 }  // namespace vplg
