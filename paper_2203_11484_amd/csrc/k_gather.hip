@@ -12,6 +12,12 @@
 // ballots decide which children the packet enters.  The traversal stack is
 // wave-uniform and lives in one VGPR across the lanes (entry i in lane i:
 // push by lane select, pop by v_readlane), so it costs no LDS at all.
+//
+// A resident grid of workgroups claims work items from a device counter:
+// whole tiles, and at the end of a long view quarter tiles (one round group of
+// VPLs each) whose sums a second kernel adds up.  A pixel's sum is fixed as
+// chunk, round-group, wave and group order, so its value never depends on how
+// the items were dealt out.
 #include <algorithm>
 
 #include "vplg_impl.h"
