@@ -79,6 +79,29 @@ def test_server_results_equal_alone(env, budget_mb, inflight):
         assert torch.equal(rad, _alone(vplg, ctx, sids[si], cam, prm))
 
 
+def test_server_large_view_equals_alone(env):
+    """A 512 x 512 request: alone, its gather splits the last tiles into round-group items (at least four
+    rounds of tiles); the server's gathers claim whole tiles.  The images must agree bit for bit."""
+    vplg, ctx, scs, sids = env
+    sc = scs[0]
+    cam = dict(sc["camera"])
+    cam["width"], cam["height"] = 512, 512
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert 64 * 64 >= 4 * 2 * cus, "the lone gather must split tiles for this view"
+    prm = scenes.default_params(k_near=128, n_far=128, d_near=sc["params"]["d_near"])
+    rad = torch.full((3, 512, 512), -1.0, dtype=torch.float32, device="cuda")
+    srv = vplg.server_start(ctx, 512 << 20, max_inflight=2, n_streams=2)
+    try:
+        r = vplg.make_request(sids[0], cam, prm, rad)
+        t = vplg.server_submit(srv, r)
+        assert vplg.server_wait(srv, t, timeout_ms=120000)["state"] == vplg.REQ_DONE
+    finally:
+        vplg.server_stop(srv)
+    alone = _alone(vplg, ctx, sids[0], cam, prm)
+    assert (alone > 0).any()
+    assert torch.equal(rad, alone)
+
+
 def test_server_rejects_and_cancels(env):
     vplg, ctx, scs, sids = env
     si, cam, prm = _requests(scs, 1, seed=5)[0]
