@@ -314,7 +314,8 @@ def main():
     ap.add_argument("--tile-vpl", type=int, default=0, help="waves (VPL slices) per 8x8 pixel tile, 0 = default")
     ap.add_argument("--autotune", action="store_true", help="batch64: autotune tile_vpl per view-shape bucket")
     ap.add_argument("--requests", type=int, default=64, help="serve: requests after 8 warm-ups")
-    ap.add_argument("--scenes", default="cornell,room20k,room200k", help="quality: workloads of the study")
+    ap.add_argument("--scenes", default="cornell,cornell_point,room20k,room200k",
+                    help="quality: workloads of the study")
     ap.add_argument("--ref-vpls", type=int, default=262144, help="quality: VPLs of the dense-IR reference")
     ap.add_argument("--in-flight", type=int, default=1,
                     help="frames in flight (2: the next frame's G-buffer and VPLs are made while the current one "

@@ -194,11 +194,14 @@ def default_params(**kw):
 # ---------------------------------------------------------------------------
 
 
-def cornell(seed=0, width=128, height=128, **params):
+def cornell(seed=0, width=128, height=128, light="quad", **params):
     """Cornell-style box: 5 walls + 2 boxes (5 faces each) + 2 light triangles = 32.
 
     Unit room [0,1]^3 open at z = 0, one 0.25 x 0.25 one-sided quad light just
     below the ceiling facing down, per-face RGB albedo U[0.5, 0.8].
+    light="point": the light-model ablation -- an isotropic point light of the
+    same power at the quad's centre, lowered to y = 0.9 (one patch size below
+    the ceiling) and without the emitter triangles (30 triangles).
     """
     rng = np.random.default_rng(seed)
     b = _Builder()
@@ -218,10 +221,14 @@ def cornell(seed=0, width=128, height=128, **params):
         for face in _box_faces(c, np.asarray(h), R, 1, skip_bottom=True):
             b.add(face, rng.uniform(0.5, 0.8, 3))
     corner, eu, ev = (0.375, 0.999, 0.375), (0.25, 0, 0), (0, 0, 0.25)
-    b.add(_quad_grid(corner, eu, ev, (0, -1, 0), 1, 1), (0, 0, 0), EMITTER)
+    if light == "point":
+        lt = point_light((0.5, 0.9, 0.5), (1, 1, 1))
+    else:
+        b.add(_quad_grid(corner, eu, ev, (0, -1, 0), 1, 1), (0, 0, 0), EMITTER)
+        lt = quad_light(corner, eu, ev, (1, 1, 1))
     tri, alb, flags = b.arrays()
-    return dict(name="cornell", tri=tri, albedo=alb, flags=flags,
-                light=quad_light(corner, eu, ev, (1, 1, 1)),
+    return dict(name="cornell" if light != "point" else "cornell_point", tri=tri, albedo=alb, flags=flags,
+                light=lt,
                 camera=make_camera((0.5, 0.5, -1.0), (0.5, 0.5, 0.5), (0, 1, 0), 40.0, width, height),
                 params=default_params(**params))
 
@@ -304,7 +311,12 @@ def room200k(seed=2, width=1920, height=1080, **params):
     return procedural_room(seed, 60, 8, 30, 4, width=width, height=height, name="room200k", **p)
 
 
-WORKLOADS = {"cornell": cornell, "room20k": room20k, "room200k": room200k}
+def cornell_point(**kw):
+    """The Cornell box lit by an isotropic point light instead of the quad (light-model ablation)."""
+    return cornell(light="point", **kw)
+
+
+WORKLOADS = {"cornell": cornell, "cornell_point": cornell_point, "room20k": room20k, "room200k": room200k}
 
 
 def make_scene(name, **kw):

@@ -213,7 +213,8 @@ GEN_VARIANTS = [("cornell", {}), ("room20k", {}), ("room200k", {}), ("cornell", 
                 ("cornell", {"jitter": 1}), ("cornell", {"brightness": 1}), ("room20k", {"jitter": 1, "brightness": 1}),
                 ("room200k", {"brightness": 1}), ("cornell", {"walk_schedule": 1}),
                 ("room20k", {"walk_schedule": 1}), ("room20k", {"walk_schedule": 1, "walk_near": 1}),
-                ("cornell", {"walk_schedule": 1, "d_near": 0.0})]
+                ("cornell", {"walk_schedule": 1, "d_near": 0.0}), ("cornell_point", {}),
+                ("cornell_point", {"brightness": 1})]
 
 
 @pytest.mark.parametrize("name,variant", GEN_VARIANTS,
