@@ -100,6 +100,11 @@ def test_direct_cornell_quad_light(vplg, ctx, size):
     _check_direct(vplg, ctx, scenes.make_scene("cornell", width=size[0], height=size[1]), f"cornell {size}")
 
 
+def test_direct_cornell_point_light(vplg, ctx):
+    """The light-model ablation's Cornell box: a point light inside the box, every pixel."""
+    _check_direct(vplg, ctx, scenes.make_scene("cornell_point"), "cornell_point")
+
+
 def test_direct_room20k_point_light(vplg, ctx):
     """20k-triangle room with its point light, every pixel of the 512^2 image."""
     _check_direct(vplg, ctx, scenes.make_scene("room20k"), "room20k")
