@@ -111,6 +111,38 @@ def test_split_tail_equals_whole_tiles(vplg, ctx, size, tile_vpl):
     vplg.scene_release(ctx, sid)
 
 
+def test_gather_graph_replays(vplg, ctx):
+    """A lone gather (with its split tail: 512 x 512) captured into a HIP graph on a stream that has
+    already run a gather (its work memory exists), replayed three times with eager work and
+    synchronisation between replays; every replay equals the eager gather bit for bit."""
+    w = h = 512
+    sc = scenes.make_scene("cornell", width=w, height=h)
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
+    gb = vplg.GBuffer(w, h)
+    vplg.gbuffer_render(ctx, sid, sc["camera"], gb)
+    vid = vplg.vpls_generate(ctx, sid, sc["camera"], sc["params"])
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    eager = torch.zeros((3, h, w), dtype=torch.float32, device="cuda")
+    vplg.gather(ctx, sid, vid, gb, eager, sc["params"], s)
+    s.synchronize()
+    out = torch.full_like(eager, -1.0)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        vplg.gather(ctx, sid, vid, gb, out, sc["params"], s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"replay {rep}"
+        _ = (torch.ones(1 << 20, device="cuda") * 2).sum().item()
+    del g
+    vplg.vplset_release(ctx, vid)
+    vplg.scene_release(ctx, sid)
+
+
 def test_untuned_tile_vpl_rule(vplg, ctx):
     """tile_vpl 0 on an untuned shape: a lone gather takes 16 waves per tile below 32 tiles per compute
     unit (bit for bit the explicit 16), a view in a batch takes 8."""
