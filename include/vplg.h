@@ -253,9 +253,10 @@ typedef struct {
  * claimed in four parts each, whose sums a second kernel on the stream adds
  * up.  Gathers on one stream are ordered and may share the work memory;
  * gathers on different streams run concurrently.  A gather captured into a
- * HIP graph keeps the work memory of the stream it was captured on: do not
- * replay it concurrently with other gathers on that stream or with another
- * replay. */
+ * HIP graph keeps the work memory of the stream it was captured on: capture
+ * on a stream that has already run a gather (the first one allocates that
+ * memory, which a capture may refuse), and do not replay the graph
+ * concurrently with other gathers on that stream or with another replay. */
 int vplg_gather(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                 float* const radiance[3], const vplg_gather_params* p, void* stream);
 
