@@ -249,9 +249,10 @@ typedef struct {
  * The launch is a resident grid whose workgroups claim 8 x 8 tiles from a
  * counter in work memory that the library keeps for `stream` (about 6 MB,
  * allocated on the stream's first gather, outside the context's budget;
- * the counter is reset by a kernel before each launch).  The last tiles are
- * claimed in four parts each, whose sums a second kernel on the stream adds
- * up.  Gathers on one stream are ordered and may share the work memory;
+ * the counter is reset by a kernel before each launch).  In a view of at
+ * least four rounds of tiles (tiles >= 4 x resident workgroups) the last two
+ * rounds are claimed in four parts each, whose sums a second kernel on the
+ * stream adds up.  Gathers on one stream are ordered and may share the work memory;
  * gathers on different streams run concurrently.  A gather captured into a
  * HIP graph keeps the work memory of the stream it was captured on: capture
  * on a stream that has already run a gather (the first one allocates that
