@@ -143,6 +143,38 @@ def test_gather_graph_replays(vplg, ctx):
     vplg.scene_release(ctx, sid)
 
 
+def test_concurrent_gathers_on_two_streams(vplg, ctx):
+    """Two lone gathers with split tails (512 x 512) running at once on two streams, over different VPL
+    sets: each stream has its own work memory (tile counter, round-group sums), so each result equals
+    the same gather run alone, bit for bit."""
+    w = h = 512
+    sc = scenes.make_scene("cornell", width=w, height=h)
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
+    gb = vplg.GBuffer(w, h)
+    vplg.gbuffer_render(ctx, sid, sc["camera"], gb)
+    vids = [vplg.vpls_generate(ctx, sid, sc["camera"], sc["params"]),
+            vplg.vpls_generate(ctx, sid, sc["camera"], dict(sc["params"], k_near=128, n_far=384))]
+    torch.cuda.synchronize()
+    refs = []
+    for vid in vids:
+        r = torch.zeros((3, h, w), dtype=torch.float32, device="cuda")
+        vplg.gather(ctx, sid, vid, gb, r, sc["params"])
+        torch.cuda.synchronize()
+        refs.append(r)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(2):
+        outs = [torch.full_like(refs[0], -1.0) for _ in vids]
+        torch.cuda.synchronize()
+        for i in range(2):
+            vplg.gather(ctx, sid, vids[i], gb, outs[i], sc["params"], streams[i])
+        torch.cuda.synchronize()
+        for i in range(2):
+            assert torch.equal(outs[i], refs[i]), f"rep {rep} stream {i}"
+    for vid in vids:
+        vplg.vplset_release(ctx, vid)
+    vplg.scene_release(ctx, sid)
+
+
 def test_untuned_tile_vpl_rule(vplg, ctx):
     """tile_vpl 0 on an untuned shape: a lone gather takes 16 waves per tile below 32 tiles per compute
     unit (bit for bit the explicit 16), a view in a batch takes 8."""
