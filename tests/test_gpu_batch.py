@@ -1,4 +1,6 @@
-"""Batched gather (one persistent, graph-replayed launch over many views) and the tile autotuner."""
+"""Batched gather (one persistent, graph-replayed launch over many views), the tile autotuner, and how a lone
+gather's work is dealt out: its split tail equals whole tiles, a captured gather replays bit for bit, and
+gathers on two streams at once keep to their own work memory."""
 import os
 
 import numpy as np
