@@ -212,6 +212,8 @@ def bench_serve(args):
             time.sleep(0.0005)
         plain(n_warm + j)
         lat_plain.append(time.perf_counter() - t0 - arrivals[j])
+        if (j + 1) % 64 == 0:
+            print(f"bench: plain FIFO loop, {j + 1}/{n} requests done", file=sys.stderr, flush=True)
     span_plain = time.perf_counter() - t0
     ref = [outs[n_warm + j].clone() for j in range(n)]
     for j in range(n):
@@ -229,7 +231,10 @@ def bench_serve(args):
         r = vplg.make_request(sids[si], cam, prm, outs[n_warm + j])
         keep.append(r)
         tickets.append(vplg.server_submit(srv, r))
+        if (j + 1) % 64 == 0:
+            print(f"bench: server, {j + 1}/{n} requests submitted", file=sys.stderr, flush=True)
     times = [vplg.server_wait(srv, tk, timeout_ms=600000) for tk in tickets]
+    print("bench: server, every request done", file=sys.stderr, flush=True)
     st = vplg.server_query(srv)
     vplg.server_stop(srv)
     torch.cuda.synchronize()
