@@ -443,12 +443,6 @@ __global__ void k_classify(DevScene s, CamBasis cb, DevLight dl, GenParams p, Ge
     if (pos >= 0) b.sortbuf[s_base + pos] = key;
 }
 
-__global__ void k_fill_u64(unsigned long long* p, long long from, long long to, unsigned long long v)
-{
-    long long i = from + (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < to) p[i] = v;
-}
-
 constexpr int kLocal = 2048;  // elements per workgroup in the LDS stages
 
 // The sort runs on the front of the buffer that holds the eligible keys: the
@@ -644,6 +638,12 @@ __global__ void k_strata_state(GenParams p, GenBuffers b, double rho_bar)
         b.state->keller_n = N;
         double rr = 1.0;
         for (int j = 0; j < p.max_bounces; ++j) { b.state->keller_t[j] = (long long)floor(rr * (double)N); rr *= rho_bar; }
+    }
+    // a zero far target needs no path at all
+    if (b.state->n_far_target == 0) {
+        b.state->walk_done = 1;
+        b.state->n_far = 0;
+        b.state->n_paths = 0;
     }
 }
 
@@ -946,15 +946,6 @@ __global__ __launch_bounds__(COLLECT_T) void k_walk_collect(GenParams p, GenBuff
 }
 
 // A zero far target needs no path at all.
-__global__ void k_walk_begin(GenBuffers b)
-{
-    if (b.state->n_far_target == 0) {
-        b.state->walk_done = 1;
-        b.state->n_far = 0;
-        b.state->n_paths = 0;
-    }
-}
-
 // Divide far fluxes by the number of paths; I = flux / pi; write float VPLs.
 __global__ void k_walk_finish(DevScene s, GenBuffers b, DevVpls v)
 {
@@ -978,7 +969,7 @@ __global__ void k_walk_finish(DevScene s, GenBuffers b, DevVpls v)
     v.nx[o] = (float)nt.x; v.ny[o] = (float)nt.y; v.nz[o] = (float)nt.z;
 }
 
-__global__ void k_state_init(GenBuffers b, long long n_patches)
+__device__ void state_init(const GenBuffers& b, long long n_patches)
 {
     GenState* st = b.state;
     st->n_patches = n_patches;
@@ -987,6 +978,15 @@ __global__ void k_state_init(GenBuffers b, long long n_patches)
     st->flags = st->near_discarded = 0;
     st->keller_n = st->keller_t[0] = st->keller_t[1] = st->keller_t[2] = 0;
     st->walk_done = 0;
+}
+
+// The generation's state zeroed and the sort buffer filled with all-ones
+// keys (one launch: both precede the classification).
+__global__ void k_init_fill(GenBuffers b, long long n_patches, long long n2)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) state_init(b, n_patches);
+    if (i < n2) b.sortbuf[i] = ~0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -1062,6 +1062,34 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_apply(const long long* in, int 
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = sums[gridDim.x];
 }
 
+// Small inputs: the whole exclusive scan in one workgroup, tile by tile with
+// a running carry (integers: the same values as the three phases, in one
+// launch instead of three).
+constexpr int kScanSmallTiles = 16;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_small(const long long* in, int n, long long* out)
+{
+    long long carry = 0;
+    for (long long base = 0; base < n; base += SCAN_TILE) {
+        long long v[SCAN_E];
+        long long acc = 0;
+        for (int e = 0; e < SCAN_E; ++e) {
+            long long i = base + (long long)threadIdx.x * SCAN_E + e;
+            v[e] = i < n ? in[i] : 0;
+            acc += v[e];
+        }
+        long long total;
+        long long ex = block_excl_scan(acc, &total) + carry;
+        for (int e = 0; e < SCAN_E; ++e) {
+            long long i = base + (long long)threadIdx.x * SCAN_E + e;
+            if (i < n) out[i] = ex;
+            ex += v[e];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 inline unsigned nblocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -1073,6 +1101,10 @@ hipError_t launch_scan_i64(const long long* in, long long* out, int n, long long
     int nb = (int)nblocks(n, SCAN_TILE);
     if (nb < 1) nb = 1;
     if (tmp_len < nb + 1) return hipErrorInvalidValue;
+    if (nb <= kScanSmallTiles) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(SCAN_T), 0, s, in, n, out);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_T), 0, s, in, n, tmp);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_T), 0, s, tmp, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_T), 0, s, in, n, tmp, out);
@@ -1093,8 +1125,7 @@ hipError_t launch_generate(const DevScene& sc, const DevLight& L, const CamBasis
     long long NP = b.n_patches;
     long long n2 = kLocal;
     while (n2 < NP) n2 <<= 1;
-    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, b, NP);
-    hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(n2, GB)), dim3(GB), 0, s, b.sortbuf, 0ll, n2, ~0ull);
+    hipLaunchKernelGGL(k_init_fill, dim3(nblocks(n2, GB)), dim3(GB), 0, s, b, NP, n2);
     if (NP > 0) hipLaunchKernelGGL(k_classify, dim3(nblocks(NP, GB)), dim3(GB), 0, s, sc, cam, L, p, b);
     // bitonic sort: LDS stages for j < kLocal, global passes above; the
     // network is launched for every patch, and its passes skip what lies past
@@ -1128,8 +1159,8 @@ hipError_t launch_generate(const DevScene& sc, const DevLight& L, const CamBasis
     }
     hipLaunchKernelGGL(k_strata_state, dim3(1), dim3(1), 0, s, p, bb, sc.rho_bar);
     // the walk: batches until the far target is met or max_paths is reached
-    // (batches after that exit at once)
-    hipLaunchKernelGGL(k_walk_begin, dim3(1), dim3(1), 0, s, bb);
+    // (batches after that exit at once; k_strata_state marks a zero target
+    // done)
     long long start = 0;
     // the walk is latency-bound (one serial path per thread): every batch
     // takes the whole capacity; deposits are kept in path order, so the batch
