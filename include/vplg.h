@@ -317,9 +317,11 @@ typedef struct {
  * the replay.  Every view's radiance is identical to vplg_gather's with the
  * same resolved tile_vpl, whatever else is in the batch.  A batch that holds
  * a 16-wave view runs in 16-wave workgroups (a second graph, captured on
- * first use), else in 8-wave ones.  Calls on one context must
- * not overlap (they share the work table); the call waits only for the
- * previous call's table copy. */
+ * first use), else in 8-wave ones.  Every call shares the context's work
+ * table, so calls are ordered on the device: a call's table copies wait (on
+ * `stream`) for the previous call's replay, on whatever stream it ran.  The
+ * host thread waits only for the previous call's table copy.  Calls on one
+ * context from several host threads must be serialised by the caller. */
 int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views, void* stream);
 
 /* Time vplg_gather with tile_vpl 1, 2, 4, 8 and 16 on this view (synchronises

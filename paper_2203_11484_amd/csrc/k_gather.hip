@@ -31,10 +31,7 @@ constexpr int kGatherMaxWaves = 16;     // waves per gather workgroup (VPL slice
 constexpr int kGatherMaxThreads = 64 * kGatherMaxWaves;
 constexpr int kChunk = 16;              // VPLs per first-level partial sum of a wave
 constexpr int kGroups = 4;              // round groups of a tile (the split granularity of the tail)
-#ifndef VPLG_SPLIT_ROUNDS
-#define VPLG_SPLIT_ROUNDS 2
-#endif
-constexpr int kSplitRounds = VPLG_SPLIT_ROUNDS;  // split tiles per workgroup of the launch
+constexpr int kSplitRounds = 2;         // split tiles per workgroup of the launch
 constexpr float kInvPi = 0.318309886183790671538f;
 
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }

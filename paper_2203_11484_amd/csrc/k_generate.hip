@@ -749,10 +749,7 @@ __device__ __forceinline__ void strata_block(const DevScene& s, const DevLight& 
 // the render server those extra waves share the SIMDs with the other
 // requests' gathers and the served median latency rises by about a tenth:
 // full 64-lane waves are kept.
-#ifndef VPLG_WALK_LANES
-#define VPLG_WALK_LANES 64
-#endif
-constexpr int kWalkLanes = VPLG_WALK_LANES;
+constexpr int kWalkLanes = 64;
 
 // (block `blk` of the batch's blocks; no barrier inside)
 __device__ __forceinline__ void walk_block(const DevScene& s, const DevLight& dl, const GenParams& p, const GenBuffers& b,

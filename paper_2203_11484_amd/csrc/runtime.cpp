@@ -217,6 +217,7 @@ int vplg_context_destroy(vplg_context* ctx)
     }
     if (be.capture) (void)hipStreamDestroy(be.capture);
     if (be.staged) (void)hipEventDestroy(be.staged);
+    if (be.replayed) (void)hipEventDestroy(be.replayed);
     if (be.d_tab) (void)hipFree(be.d_tab);
     if (be.d_views) (void)hipFree(be.d_views);
     if (be.d_counter) (void)hipFree(be.d_counter);
@@ -994,6 +995,7 @@ static int batch_init(vplg_context* ctx, int wide)
         HIPCHK(hipHostMalloc(&be.h_tab, sizeof(BatchTable), hipHostMallocDefault));
         HIPCHK(hipHostMalloc(&be.h_views, sizeof(GatherArgs) * kBatchMaxViews, hipHostMallocDefault));
         HIPCHK(hipEventCreateWithFlags(&be.staged, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&be.replayed, hipEventDisableTiming));
         HIPCHK(hipStreamCreateWithFlags(&be.capture, hipStreamNonBlocking));
         be.ready = true;
     }
@@ -1061,10 +1063,14 @@ int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views
     be.h_tab->prefix[n_views] = (int)total;
     be.h_tab->n_views = n_views;
     hipStream_t s = (hipStream_t)stream;
+    // the device table, views and counter are shared by every call: this
+    // call's copies wait for the previous replay, whatever stream it ran on
+    HIPCHK(hipStreamWaitEvent(s, be.replayed, 0));
     HIPCHK(hipMemcpyAsync(be.d_tab, be.h_tab, sizeof(BatchTable), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(be.d_views, be.h_views, sizeof(GatherArgs) * n_views, hipMemcpyHostToDevice, s));
     HIPCHK(hipEventRecord(be.staged, s));
     HIPCHK(hipGraphLaunch(be.exec[wide], s));
+    HIPCHK(hipEventRecord(be.replayed, s));
     return VPLG_OK;
 }
 

@@ -74,6 +74,7 @@ struct BatchEngine {
     BatchTable* h_tab = nullptr;
     GatherArgs* h_views = nullptr;
     hipEvent_t staged = nullptr;  // last use of the pinned staging
+    hipEvent_t replayed = nullptr;  // end of the last replay (the device table's last reader)
     hipStream_t capture = nullptr;
     // [0]: workgroups of 8 waves, [1]: of 16 waves (captured on first use)
     hipGraph_t graph[2] = {nullptr, nullptr};
