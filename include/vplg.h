@@ -261,6 +261,22 @@ typedef struct {
 int vplg_gather(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                 float* const radiance[3], const vplg_gather_params* p, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): vplg_gather
+ * with the same arguments, kernels and result, bit for bit, that allocates
+ * nothing.  Its work memory (the tile counter and the round-group sums of at
+ * most 2,048 split tiles: 6,291,712 bytes) is a fixed device array of the
+ * library, one per device, held until the process ends; its address is looked
+ * up by vplg_context_create.  The split tail is capped at 2,048 tiles, so no
+ * view is too large for the array; the call checks that bound and returns
+ * VPLG_EINVAL if a launch would need more.  Every call on one device shares
+ * the array and overwrites what the last call left (the counter is reset by a
+ * kernel on `stream` before each launch): calls that overlap on one device,
+ * from any context, stream or thread, race and give wrong results.  Order
+ * them on one stream, or wait for one before starting the next. */
+int vplg_gather_noalloc(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                        float* const radiance[3], const vplg_gather_params* p, void* stream);
+
 /* The same kernel, instrumented: also adds to counters[0..7] (device uint64)
  * the pairs evaluated, shadow rays cast, BVH node visits and ray-triangle
  * tests of active lanes, then, per wave, packets traced, packet node steps,

@@ -19,6 +19,7 @@
 // chunk, round-group, wave and group order, so its value never depends on how
 // the items were dealt out.
 #include <algorithm>
+#include <mutex>
 
 #include "vplg_impl.h"
 
@@ -33,6 +34,15 @@ constexpr int kChunk = 16;              // VPLs per first-level partial sum of a
 constexpr int kGroups = 4;              // round groups of a tile (the split granularity of the tail)
 constexpr int kSplitRounds = 2;         // split tiles per workgroup of the launch
 constexpr float kInvPi = 0.318309886183790671538f;
+
+// Work memory of the allocation-free gather: the tile counter in the first
+// 256 bytes, then the round-group sums of at most kScratchSplitTiles split
+// tiles (6,291,712 bytes in all).  A file-scope device array: every device
+// the library runs on holds its own copy until the process ends, and every
+// allocation-free gather on that device shares it.
+constexpr int kScratchSplitTiles = 2048;
+constexpr size_t kScratchBytes = 256 + (size_t)kScratchSplitTiles * kGroups * 3 * 64 * sizeof(float);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -897,6 +907,47 @@ hipError_t gather_occupancy(int waves, bool counted, int* blocks_per_cu)
 }
 
 int gather_split_floats_per_tile() { return kGroups * 3 * 64; }
+
+// Device address of `scratch` per device.  In host code the array's name is
+// only a host-side handle, so launches take the address looked up here.
+namespace {
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t gather_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[device] = p;
+    return hipSuccess;
+}
+
+void* gather_scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_addr[device];
+}
+
+size_t gather_scratch_bytes() { return kScratchBytes; }
+
+int gather_scratch_split_cap() { return kScratchSplitTiles; }
+
+hipError_t launch_gather_scratch(const GatherArgs& a, void* scr, int blocks, hipStream_t s)
+{
+    if (!scr) return hipErrorInvalidValue;
+    GatherArgs b = a;
+    b.split_cap = kScratchSplitTiles;
+    b.split_part = reinterpret_cast<float*>(static_cast<unsigned char*>(scr) + 256);
+    return launch_gather(b, false, static_cast<unsigned int*>(scr), blocks, s);
+}
 
 hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counter, int blocks, hipStream_t s)
 {

@@ -193,6 +193,9 @@ int vplg_context_create(int device, uint64_t hbm_budget_bytes, vplg_context** ou
     HIPCHK(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(VPLG_EINVAL, "device %d out of range (%d devices)", device, n);
     HIPCHK(hipSetDevice(device));
+    // the allocation-free gather's work memory: its address on this device
+    hipError_t e = gather_scratch_setup(device);
+    if (e != hipSuccess) return fail(VPLG_EHIP, "gather scratch address on device %d: %s", device, hipGetErrorString(e));
     auto* ctx = new vplg_context;
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
@@ -875,6 +878,20 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
     return VPLG_OK;
 }
 
+int gather_grid(vplg_context* ctx, int waves, bool counted, int* blocks)
+{
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->cus == 0) HIPCHK(hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const int lw = __builtin_ctz((unsigned)waves);
+    int& per_cu = ctx->gather_blocks[counted ? 1 : 0][lw];
+    if (per_cu == 0) {
+        HIPCHK(gather_occupancy(waves, counted, &per_cu));
+        if (per_cu < 1) per_cu = 1;
+    }
+    *blocks = ctx->cus * per_cu;
+    return VPLG_OK;
+}
+
 int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s, bool split_tail)
 {
     GatherWork wk;
@@ -893,15 +910,9 @@ int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t
         } else {
             wk = it->second;
         }
-        if (ctx->cus == 0) HIPCHK(hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-        const int lw = __builtin_ctz((unsigned)a.waves_per_tile);
-        int& per_cu = ctx->gather_blocks[counted ? 1 : 0][lw];
-        if (per_cu == 0) {
-            HIPCHK(gather_occupancy(a.waves_per_tile, counted, &per_cu));
-            if (per_cu < 1) per_cu = 1;
-        }
-        blocks = ctx->cus * per_cu;
     }
+    int rc = gather_grid(ctx, a.waves_per_tile, counted, &blocks);
+    if (rc) return rc;
     GatherArgs b = a;
     b.split_cap = split_tail ? kGatherSplitCap : 0;
     b.split_part = wk.part;
@@ -921,6 +932,25 @@ int vplg_gather(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const 
     int rc = gather_common(ctx, scene_id, vplset_id, gb, radiance, p, &a);
     if (rc) return rc;
     return run_gather(ctx, a, false, (hipStream_t)stream);
+}
+
+int vplg_gather_noalloc(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
+                        float* const radiance[3], const vplg_gather_params* p, void* stream)
+{
+    GatherArgs a;
+    int rc = gather_common(ctx, scene_id, vplset_id, gb, radiance, p, &a);
+    if (rc) return rc;
+    void* scr = gather_scratch_address(ctx->device);
+    if (!scr) return fail(VPLG_EHIP, "device %d: the gather's scratch array has no address", ctx->device);
+    int blocks = 0;
+    if ((rc = gather_grid(ctx, a.waves_per_tile, false, &blocks))) return rc;
+    // the launch splits at most gather_scratch_split_cap() tiles, whatever
+    // the view's size; check the bound the array was sized for all the same
+    const size_t need = 256 + sizeof(float) * (size_t)gather_scratch_split_cap() * gather_split_floats_per_tile();
+    if (need > gather_scratch_bytes())
+        return fail(VPLG_EINVAL, "gather scratch: %zu bytes needed, %zu available", need, gather_scratch_bytes());
+    HIPCHK(launch_gather_scratch(a, scr, blocks, (hipStream_t)stream));
+    return VPLG_OK;
 }
 
 int vplg_gather_counted(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,

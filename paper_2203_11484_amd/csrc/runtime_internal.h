@@ -163,6 +163,8 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
 // split_tail = false: whole tiles only (for gathers that share the GPU with
 // others, where no one view's tail leaves it idle); the result is the same.
 int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s, bool split_tail = true);
+// resident workgroups of the single-view gather for `waves` waves per tile (cached per context)
+int gather_grid(vplg_context* ctx, int waves, bool counted, int* blocks);
 
 }  // namespace rt
 }  // namespace vplg

@@ -215,6 +215,18 @@ hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counte
 hipError_t gather_occupancy(int waves, bool counted, int* blocks_per_cu);
 // Floats of split-tile work memory per tile (its round groups' sums).
 int gather_split_floats_per_tile();
+// Allocation-free gather: its work memory is a fixed device array of the
+// library (one per device).  Setup looks up the array's device address on the
+// current device (once per device; call with `device` current); the address
+// is then what the launches take.  Until setup has run on a device its
+// address is null.
+hipError_t gather_scratch_setup(int device);
+void* gather_scratch_address(int device);
+size_t gather_scratch_bytes();
+int gather_scratch_split_cap();
+// The persistent single-view gather with its tile counter and split-tile sums
+// in `scratch` (an address from gather_scratch_address).
+hipError_t launch_gather_scratch(const GatherArgs& a, void* scratch, int blocks, hipStream_t s);
 hipError_t launch_vis_dump(const VisDumpArgs& a, hipStream_t s);
 hipError_t launch_gather_batch(const BatchTable* tab, const GatherArgs* views, unsigned int* counter, int blocks,
                                int block_waves, hipStream_t s);

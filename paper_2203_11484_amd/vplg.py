@@ -115,6 +115,8 @@ _SIGS = {
     "vplg_vplset_debug": (C.c_int, [_p, _u64, C.c_int32, _p, C.c_int64, C.POINTER(C.c_int64)]),
     "vplg_vplset_release": (C.c_int, [_p, _u64]),
     "vplg_gather": (C.c_int, [_p, _u64, _u64, C.POINTER(GBufferStruct), C.POINTER(_p), C.POINTER(GatherParams), _p]),
+    "vplg_gather_noalloc": (C.c_int, [_p, _u64, _u64, C.POINTER(GBufferStruct), C.POINTER(_p),
+                                      C.POINTER(GatherParams), _p]),
     "vplg_gather_counted": (C.c_int, [_p, _u64, _u64, C.POINTER(GBufferStruct), C.POINTER(_p),
                                       C.POINTER(GatherParams), _p, _p]),
     "vplg_gather_visibility_dump": (C.c_int, [_p, _u64, _u64, C.POINTER(GBufferStruct), _p, C.c_int32, _p,
@@ -391,6 +393,13 @@ def gather(ctx, scene_id, vplset_id, gb, radiance, params=None, stream=None):
     gp = params if isinstance(params, GatherParams) else make_gather_params(params)
     _check(lib().vplg_gather(ctx, scene_id, vplset_id, C.byref(gb.struct), radiance_planes(radiance), C.byref(gp),
                              _stream(stream)))
+
+
+def gather_noalloc(ctx, scene_id, vplset_id, gb, radiance, params=None, stream=None):
+    """vplg_gather without device allocation: its work memory is the library's fixed per-device array."""
+    gp = params if isinstance(params, GatherParams) else make_gather_params(params)
+    _check(lib().vplg_gather_noalloc(ctx, scene_id, vplset_id, C.byref(gb.struct), radiance_planes(radiance),
+                                     C.byref(gp), _stream(stream)))
 
 
 def direct(ctx, scene_id, gb, radiance, t_eps=1e-4, stream=None):
