@@ -23,7 +23,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published)
 # algorithmic FLOPs (FMA = 2; min, max and compares not counted): per pair of
 # the shading formula; per cast shadow ray its slab set-up (3 reciprocals, 3
 # products) and watertight set-up (reciprocal, 2 shear products, |d|^2/d_kz^2);
-# per visited BVH2 node (two slab tests of 6 FMAs); per watertight triangle
+# per BVH2 node the ray's own segment entered (two slab tests of 6 FMAs); per
+# triangle of a leaf the ray's own segment entered, one watertight
 # test (9 differences, 6 shear FMAs, 3 edge functions, determinant, T, t and
 # the parallel cut)
 FLOP_PAIR, FLOP_RAY, FLOP_NODE, FLOP_TRI = 27, 13, 24, 44
@@ -442,10 +443,11 @@ def main():
           file=sys.stderr, flush=True)
 
     # instrumented launch (untimed): pairs, shadow rays, BVH nodes, triangle tests
-    cnt = torch.zeros(8, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(vplg.N_COUNTERS, dtype=torch.int64, device="cuda")
     vplg.gather_counted(ctx, sid, vid, gb, rad, cnt, gp, stream)
     torch.cuda.synchronize()
-    pairs_c, rays, nodes, tris, packets, psteps, plane, ptris = (int(x) for x in cnt.cpu().tolist())
+    (pairs_c, rays, nodes, tris, packets, psteps, plane, ptris, rides, both, pops, pk_blocked, pk_clear,
+     blocked) = (int(x) for x in cnt.cpu().tolist())
     stats = vplg.vplset_stats(ctx, vid)
     valid = int((gb.tri >= 0).sum().item())
 
@@ -486,12 +488,16 @@ def main():
         "p99_frame_ms": float(np.percentile(frame_ms, 99)),
         "valid_pixel_frac": valid / P,
         "shadow_ray_frac": rays / max(pairs_c, 1),
+        "blocked_ray_frac": blocked / max(rays, 1),
         "nodes_per_ray": nodes / max(rays, 1),
         "tris_per_ray": tris / max(rays, 1),
         "ray_tri_tests_per_s": tris / g_mean_s,
         "packets": {"count": packets, "lanes_per_packet": plane / max(packets, 1),
                     "steps_per_packet": psteps / max(packets, 1), "tri_steps_per_packet": ptris / max(packets, 1),
-                    "lane_efficiency_nodes": nodes / max(64 * psteps, 1)},
+                    "lane_efficiency_nodes": nodes / max(64 * psteps, 1),
+                    "rider_frac": (rides - nodes) / max(rides, 1),
+                    "both_children_frac": both / max(psteps, 1), "pop_frac": pops / max(psteps, 1),
+                    "all_blocked_frac": pk_blocked / max(packets, 1), "none_blocked_frac": pk_clear / max(packets, 1)},
         "generation": {k: int(stats[k]) for k in ("n_patches", "n_near", "n_eligible", "n_paths")},
     }
     if not args.no_cpu:

@@ -277,11 +277,16 @@ int vplg_gather(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const 
 int vplg_gather_noalloc(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                         float* const radiance[3], const vplg_gather_params* p, void* stream);
 
-/* The same kernel, instrumented: also adds to counters[0..7] (device uint64)
- * the pairs evaluated, shadow rays cast, BVH node visits and ray-triangle
- * tests of active lanes, then, per wave, packets traced, packet node steps,
- * active lanes at packet start and packet triangle steps.  For measurement;
- * slower than vplg_gather. */
+/* The same kernel, instrumented: also adds to counters[0..13] (device
+ * uint64) the pairs evaluated, shadow rays cast, BVH node visits of each
+ * ray's own traversal (inner nodes whose box its own segment entered, two
+ * child slab tests each) and its ray-triangle tests (triangles of leaves its
+ * own segment entered); then, per wave, packets traced, packet node steps,
+ * active lanes at packet start and packet triangle steps; then node steps
+ * ridden by unblocked lanes (own or not), packet steps entering both
+ * children, packet steps entering neither, packets with every ray blocked,
+ * packets with no ray blocked, and shadow rays blocked.  The radiance is the
+ * plain gather's.  For measurement; slower than vplg_gather. */
 int vplg_gather_counted(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                         float* const radiance[3], const vplg_gather_params* p, uint64_t* counters, void* stream);
 

@@ -85,10 +85,18 @@ __device__ __forceinline__ float safe_inv(float d)
     return rcpf(fabsf(d) > 1e-30f ? d : copysignf(1e-30f, d));
 }
 
+// Counters of the instrumented gather.  Per lane: shadow rays cast, BVH node
+// visits of the ray's own traversal (nodes its segment entered), triangle
+// tests of the ray's own traversal, node steps the lane rode along unblocked
+// (its own and the packet's), and rays found blocked.  Per wave: packets
+// traced, packet node steps, active lanes at packet start, packet triangle
+// steps, steps entering both children, steps entering neither (a pop), and
+// packets with every ray blocked or none.
+constexpr int kCounters = 14;
 struct Counters {
     unsigned long long rays = 0, nodes = 0, tris = 0;
-    // wave-level: packets traced, packet node steps, active lanes at packet start, packet triangle steps
     unsigned long long packets = 0, psteps = 0, plane = 0, ptris = 0;
+    unsigned long long rides = 0, both = 0, pops = 0, pk_blocked = 0, pk_clear = 0, blocked = 0;
 };
 
 // Per-ray set-up of the watertight ray/triangle test (Woop, Benthin and
@@ -331,13 +339,21 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
     int slot = 0;
     int sp = 0;
     int node = 0;
+    // instrumented only: the lanes whose own segment entered `node` (the
+    // parent's slab test of that child passed for them), kept on a second
+    // stack beside the node index
+    unsigned long long entered = alive;
+    unsigned int slot_lo = 0, slot_hi = 0;
     while (true) {
         const Rec nd = load_rec(nodes, node);
         const float4 n0 = nd.q0, n1 = nd.q1, n2 = nd.q2, n3f = nd.q3;
         const int c0 = __float_as_int(n3f.x), c1 = __float_as_int(n3f.y);
         const int kk = __float_as_int(n3f.z), axis = __float_as_int(n3f.w);
-        if (COUNT && lane_bit(alive, lane)) cnt.nodes++;
-        if (COUNT && lane == 0) cnt.psteps++;
+        if (COUNT) {
+            if (lane_bit(entered & alive, lane)) cnt.nodes++;
+            if (lane_bit(alive, lane)) cnt.rides++;
+            if (lane == 0) cnt.psteps++;
+        }
         float lo0, hi0, lo1, hi1;
         seg_boxes<OCT>(n0, n1, n2, r, &lo0, &hi0, &lo1, &hi1);
         unsigned long long b0 = ballot(lo0 < hi0) & alive;
@@ -363,17 +379,30 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
                 // the packet's direction signs first, the other pushed
                 const bool first1 = (oct >> axis) & 1;
                 slot = lane == sp ? (first1 ? c0 : c1) : slot;
+                if (COUNT) {
+                    const unsigned long long later = first1 ? b0 : b1;
+                    slot_lo = lane == sp ? (unsigned int)later : slot_lo;
+                    slot_hi = lane == sp ? (unsigned int)(later >> 32) : slot_hi;
+                    entered = first1 ? b1 : b0;
+                    if (lane == 0) cnt.both++;
+                }
                 ++sp;
                 node = first1 ? c1 : c0;
             } else {
                 node = c0;
+                if (COUNT) entered = b0;
             }
         } else if (b1) {
             node = c1;
+            if (COUNT) entered = b1;
         } else {
+            if (COUNT && lane == 0) cnt.pops++;
             if (sp == 0) break;
             --sp;
             node = __builtin_amdgcn_readlane(slot, sp);
+            if (COUNT)
+                entered = (unsigned long long)(unsigned int)__builtin_amdgcn_readlane((int)slot_lo, sp) |
+                          ((unsigned long long)(unsigned int)__builtin_amdgcn_readlane((int)slot_hi, sp) << 32);
         }
     }
     return lane_bit(alive, lane);
@@ -508,6 +537,14 @@ __device__ __forceinline__ float3 gather_tile(const GatherArgs& a, int tile, int
                 float gt = fminf(C, cp * ck * rcpf(r2 * r2));
                 bool vis = packet_visible<COUNT>(a.scene, x, y, z, dx, dy, dz, act, tlo, thi, tp, __float_as_int(v0.w),
                                                  lane, cnt);
+                if (COUNT) {
+                    const unsigned long long am = ballot(act), vm = ballot(vis);
+                    if (act && !vis) cnt.blocked++;
+                    if (lane == 0) {
+                        cnt.pk_blocked += vm == 0;
+                        cnt.pk_clear += vm == am;
+                    }
+                }
                 if (vis) {
                     const float4 v2 = load_c4(vp, 3 * k + 2);
                     pr = fmaf(v2.x, gt, pr);
@@ -565,8 +602,10 @@ __device__ __forceinline__ void flush_counters(unsigned long long* out, const Co
                                                int lane)
 {
     if (!COUNT) return;
-    unsigned long long v[8] = {pairs, cnt.rays, cnt.nodes, cnt.tris, cnt.packets, cnt.psteps, cnt.plane, cnt.ptris};
-    for (int c = 0; c < 8; ++c) {
+    const unsigned long long v[kCounters] = {pairs, cnt.rays, cnt.nodes, cnt.tris, cnt.packets, cnt.psteps, cnt.plane,
+                                             cnt.ptris, cnt.rides, cnt.both, cnt.pops, cnt.pk_blocked, cnt.pk_clear,
+                                             cnt.blocked};
+    for (int c = 0; c < kCounters; ++c) {
         unsigned long long sum = v[c];
         for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
         if (lane == 0) atomicAdd(&out[c], sum);

@@ -408,8 +408,13 @@ def direct(ctx, scene_id, gb, radiance, t_eps=1e-4, stream=None):
                              _stream(stream)))
 
 
+N_COUNTERS = 14  # counters[0..13] of vplg_gather_counted
+
+
 def gather_counted(ctx, scene_id, vplset_id, gb, radiance, counters, params=None, stream=None):
-    """counters: torch int64 tensor of 8 on the device (see vplg_gather_counted in include/vplg.h)."""
+    """counters: torch int64 tensor of N_COUNTERS on the device (see vplg_gather_counted in include/vplg.h)."""
+    if counters.numel() < N_COUNTERS:
+        raise ValueError(f"gather_counted needs {N_COUNTERS} counters")
     gp = params if isinstance(params, GatherParams) else make_gather_params(params)
     _check(lib().vplg_gather_counted(ctx, scene_id, vplset_id, C.byref(gb.struct), radiance_planes(radiance),
                                      C.byref(gp), C.c_void_p(counters.data_ptr()), _stream(stream)))
