@@ -10,7 +10,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as orc  # noqa: E402
 from paper_2203_11484_amd import scenes  # noqa: E402
-from tests import helpers as H  # noqa: E402
+from tests import oracle_check as OC  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -197,7 +197,9 @@ def test_untuned_tile_vpl_rule(vplg, ctx):
 
 
 def test_batch_view_matches_oracle(vplg, ctx):
-    """One batched view against the oracle on its own inputs (the oracle's G-buffer and VPLs)."""
+    """Batched views against the oracle under the gather's parity protocol (tests/oracle_check.py), every
+    pixel: one view on the oracle's own G-buffer and VPLs, batched beside two others, and two of the batch's
+    views on the G-buffers and VPL sets the GPU made (downloaded for the oracle)."""
     sc = scenes.make_scene("cornell", width=48, height=40)
     S = orc.Scene.from_dict(sc)
     gbo = S.gbuffer(sc["camera"])
@@ -205,16 +207,19 @@ def test_batch_view_matches_oracle(vplg, ctx):
     sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
     gb = vplg.GBuffer.from_arrays(gbo["pos"], gbo["nrm"], gbo["alb"], gbo["tri"], 48, 40)
     vid = vplg.vpls_upload(ctx, g["pos"], g["nrm"], g["I"], g["tri"])
-    other = _views(vplg, ctx)[:2]
+    views = _views(vplg, ctx)
+    other = [views[1], views[3]]
     rad = torch.zeros((3, 40, 48), dtype=torch.float32, device="cuda")
     vplg.gather_batch(ctx, other + [dict(scene=sid, vplset=vid, gb=gb, radiance=rad, params=sc["params"])])
     torch.cuda.synchronize()
     L_gpu = rad.cpu().numpy().reshape(3, -1).T
-    f = gb.to_numpy()
-    L_ref = S.gather(f["pos"], f["nrm"], f["alb"], f["tri"], g["pos"].astype(np.float32), g["nrm"].astype(np.float32),
-                     g["I"].astype(np.float32), g["tri"])
-    ok = H.radiance_close(L_gpu, L_ref)
-    assert ok.mean() > 0.995, (~ok).sum()
+    OC.check_gather(vplg, ctx, S, sid, vid, gb, L_gpu, np.arange(48 * 40), sc["params"], "batched cornell view")
+    for j, v in enumerate(other):
+        Sv = orc.Scene.from_dict(v["sc"])
+        P = v["gb"].width * v["gb"].height
+        Lv = v["radiance"].cpu().numpy().reshape(3, -1).T
+        OC.check_gather(vplg, ctx, Sv, v["scene"], v["vplset"], v["gb"], Lv, np.arange(P), v["sc"]["params"],
+                        f"batched room view {j}", min_lit=0.1)
 
 
 def test_batch_rejects_bad_views(vplg, ctx):

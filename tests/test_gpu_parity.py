@@ -1,10 +1,13 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Gather: the oracle's G-buffer and VPL set (rounded to float32) feed both
-sides.  Every visibility disagreement must be grazing (moving an endpoint by
-1e-5 of the scene diagonal flips the oracle's answer) and at most 1e-4 of the
-pairs; radiance must then match per channel within 1e-4 relative, with the
-oracle re-evaluated on the GPU's bit for the disagreeing pairs.
+sides, or (the device path) the G-buffer and VPL set the GPU made are
+downloaded and fed to the oracle.  Every visibility disagreement must be
+grazing (moving an endpoint by 1e-5 of the scene diagonal flips the oracle's
+answer) and at most 1e-4 of the pairs; radiance must then match per channel
+within 1e-4 relative, with the oracle re-evaluated on the GPU's bit for the
+disagreeing pairs (tests/oracle_check.py).
+G-buffer: the oracle's closest hit on every pixel at the workloads' sizes.
 Generation: every integer output bit-exact; floats to float32 rounding.
 """
 import numpy as np
@@ -15,6 +18,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as orc  # noqa: E402
 from paper_2203_11484_amd import scenes  # noqa: E402
 from tests import helpers as H  # noqa: E402
+from tests import oracle_check as OC  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -44,58 +48,19 @@ def _gather_gpu(vplg, ctx, sid, vid, gb, prm):
     return rad.cpu().numpy().reshape(3, -1).T.astype(np.float64)
 
 
-def _dump_gpu(vplg, ctx, sid, vid, gb, pixels, M, prm):
-    words = (M + 31) // 32
-    pix = torch.from_numpy(np.ascontiguousarray(pixels, np.int32)).cuda()
-    bits = torch.zeros((len(pixels), words), dtype=torch.int32, device="cuda")
-    vplg.gather_visibility_dump(ctx, sid, vid, gb, pix, bits, prm)
-    torch.cuda.synchronize()
-    b = bits.cpu().numpy().view(np.uint32)
-    k = np.arange(M)
-    return ((b[:, k // 32] >> (k % 32).astype(np.uint32)) & 1).astype(np.uint8)
-
-
 def _check_gather(vplg, ctx, sc, S, gbo, vp, pixels, prm, label):
-    """Full-image GPU gather; oracle on `pixels` with the visibility protocol."""
+    """Full-image GPU gather on the oracle's G-buffer and VPLs; oracle on `pixels` with the visibility
+    protocol (tests/oracle_check.py)."""
     cam = sc["camera"]
     W, Hh = cam["width"], cam["height"]
     sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
     gb = vplg.GBuffer.from_arrays(gbo["pos"], gbo["nrm"], gbo["alb"], gbo["tri"], W, Hh)
     vid = vplg.vpls_upload(ctx, vp["pos"], vp["nrm"], vp["I"], vp["tri"])
-    M = len(vp["pos"])
-    L_gpu = _gather_gpu(vplg, ctx, sid, vid, gb, prm)[pixels]
-    f = gb.to_numpy()
-    gpos, gtri = f["pos"][pixels], f["tri"][pixels]
-    vis_gpu = _dump_gpu(vplg, ctx, sid, vid, gb, pixels, M, prm)
-    vis_ref = S.vis_matrix(gpos, gtri, vp["pos"], vp["tri"], eps=prm["t_eps"])
-    dis = np.nonzero(vis_gpu != vis_ref)
-    # pairs whose shadow ray the gather casts: both cosines above the 1e-5 grazing epsilon
-    dvec = vp["pos"].astype(np.float64)[None, :, :] - gpos.astype(np.float64)[:, None, :]
-    dlen = np.linalg.norm(dvec, axis=2)
-    cp = np.einsum("pkc,pc->pk", dvec, f["nrm"][pixels].astype(np.float64)) / dlen
-    ck = -np.einsum("pkc,kc->pk", dvec, vp["nrm"].astype(np.float64)) / dlen
-    cast = (cp > 1e-5) & (ck > 1e-5) & (gtri[:, None] >= 0)
-    n_pairs = int(cast.sum())
-    n_dis_cast = int(cast[dis].sum())
-    print(f"{label}: {len(dis[0])} disagreements over all {vis_ref.size} pairs, {n_dis_cast} over {n_pairs} cast pairs")
-    if len(dis[0]):
-        xi, ki = dis
-        graz = S.grazing(gpos[xi], gtri[xi], vp["pos"][ki], vp["tri"][ki], eps=prm["t_eps"], delta_rel=1e-5)
-        for j in np.nonzero(graz == 0)[0][:20]:
-            print(f"{label}: non-grazing pair px={pixels[xi[j]]} tri_p={gtri[xi[j]]} x={gpos[xi[j]].tolist()} "
-                  f"vpl={ki[j]} tri_k={vp['tri'][ki[j]]} y={vp['pos'][ki[j]].tolist()} "
-                  f"gpu={vis_gpu[xi[j], ki[j]]} ref={vis_ref[xi[j], ki[j]]}", flush=True)
-        assert graz.all(), f"{label}: {(graz == 0).sum()} non-grazing visibility disagreements"
-    assert n_dis_cast <= 1e-4 * n_pairs + 0.5, f"{label}: {n_dis_cast} disagreements of {n_pairs} cast pairs"
-    ov = (dis[0].astype(np.int32), dis[1].astype(np.int32), vis_gpu[dis]) if len(dis[0]) else None
-    L_ref = S.gather(gpos, f["nrm"][pixels], f["alb"][pixels], gtri, vp["pos"], vp["nrm"], vp["I"], vp["tri"],
-                     C=prm["g_clamp"], eps=prm["t_eps"], overrides=ov)
-    ok = H.radiance_close(L_gpu, L_ref, rel=1e-4)
-    assert ok.all(), f"{label}: {(~ok).sum()} of {len(ok)} pixels outside 1e-4"
-    assert (L_ref > 0).mean() > 0.3
+    L_gpu = _gather_gpu(vplg, ctx, sid, vid, gb, prm)
+    out = OC.check_gather(vplg, ctx, S, sid, vid, gb, L_gpu, pixels, prm, label)
     vplg.vplset_release(ctx, vid)
     vplg.scene_release(ctx, sid)
-    return n_dis_cast, n_pairs
+    return out
 
 
 def _oracle_inputs(sc):
@@ -186,26 +151,61 @@ def test_gather_edge_cases(vplg, ctx):
     assert H.radiance_close(L1, Lr).all()
 
 
-def test_gbuffer_parity(vplg, ctx):
-    for name, size in (("cornell", (96, 80)), ("room20k", (160, 120))):
-        sc = scenes.make_scene(name, width=size[0], height=size[1])
-        S = orc.Scene.from_dict(sc)
-        ref = S.gbuffer(sc["camera"])
-        edge = S.gbuffer_edges(sc["camera"], delta=1e-5).astype(bool)
-        sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
-        gb = vplg.GBuffer(*size)
-        vplg.gbuffer_render(ctx, sid, sc["camera"], gb)
-        torch.cuda.synchronize()
-        g = gb.to_numpy()
-        same = g["tri"] == ref["tri"]
-        assert np.all(same | edge), f"{name}: {(~(same | edge)).sum()} non-edge pixels hit another triangle"
-        assert same.mean() > 0.97
-        m = same & (ref["tri"] >= 0)
-        diag = S.diag
-        assert np.abs(g["pos"][m] - ref["pos"][m]).max() < 1e-5 * diag
-        assert np.abs(g["nrm"][m] - ref["nrm"][m]).max() < 1e-6
-        assert np.array_equal(g["alb"][m], ref["alb"][m].astype(np.float32))
-        vplg.scene_release(ctx, sid)
+GBUFFER_CASES = [("cornell", (128, 128)), ("cornell", (100, 75)), ("room20k", (512, 512)), ("room20k", (160, 120)),
+                 ("room200k", (1920, 1080))]
+
+
+@pytest.mark.parametrize("name,size", GBUFFER_CASES, ids=[f"{n}-{w}x{h}" for n, (w, h) in GBUFFER_CASES])
+def test_gbuffer_parity(vplg, ctx, name, size):
+    """The G-buffer at the workloads' full sizes (and two ragged ones), every pixel: the same triangle as
+    the oracle's closest hit except where the oracle flags the pixel's ray as passing within 1e-5 of an
+    edge or of a nearer hit (there either triangle is a correct answer); on every pixel with the same
+    triangle, position within 1e-5 of the scene diagonal, the face normal within 1e-6 and the albedo exact."""
+    sc = scenes.make_scene(name, width=size[0], height=size[1])
+    S = orc.Scene.from_dict(sc)
+    ref = S.gbuffer(sc["camera"])
+    edge = S.gbuffer_edges(sc["camera"], delta=1e-5).astype(bool)
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
+    gb = vplg.GBuffer(*size)
+    vplg.gbuffer_render(ctx, sid, sc["camera"], gb)
+    torch.cuda.synchronize()
+    g = gb.to_numpy()
+    same = g["tri"] == ref["tri"]
+    print(f"gbuffer {name} {size}: {(~same).sum()} pixels on another triangle, all of {edge.sum()} flagged "
+          f"edge pixels excused", flush=True)
+    assert np.all(same | edge), f"{name}: {(~(same | edge)).sum()} non-edge pixels hit another triangle"
+    m = same & (ref["tri"] >= 0)
+    assert m.mean() > 0.5
+    diag = S.diag
+    assert np.abs(g["pos"][m] - ref["pos"][m]).max() < 1e-5 * diag
+    assert np.abs(g["nrm"][m] - ref["nrm"][m]).max() < 1e-6
+    assert np.array_equal(g["alb"][m], ref["alb"][m].astype(np.float32))
+    vplg.scene_release(ctx, sid)
+
+
+DEVICE_CASES = [("cornell", None, 0), ("room20k", 384, 11), ("room200k", 96, 13)]
+
+
+@pytest.mark.parametrize("name,n_px,seed", DEVICE_CASES, ids=[c[0] for c in DEVICE_CASES])
+def test_device_path_matches_oracle(vplg, ctx, name, n_px, seed):
+    """The whole path on the device at the workload's full size, as the bench runs it: G-buffer render,
+    VPL generation, gather.  The oracle then evaluates eq. (1) on the G-buffer and VPL set the GPU made
+    (downloaded), under the visibility protocol: every pixel of the Cornell box, seeded samples of the
+    rooms.  (The G-buffer and the generation are each held to the oracle by their own tests.)"""
+    sc = scenes.make_scene(name)
+    cam, prm = sc["camera"], sc["params"]
+    S = orc.Scene.from_dict(sc)
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
+    gb = vplg.GBuffer(cam["width"], cam["height"])
+    vplg.gbuffer_render(ctx, sid, cam, gb)
+    vid = vplg.vpls_generate(ctx, sid, cam, prm)
+    L_gpu = _gather_gpu(vplg, ctx, sid, vid, gb, prm)
+    P = cam["width"] * cam["height"]
+    pixels = np.arange(P) if n_px is None else np.sort(np.random.default_rng(seed).choice(P, n_px, replace=False))
+    nd, n = OC.check_gather(vplg, ctx, S, sid, vid, gb, L_gpu, pixels, prm, f"device path {name}")
+    print(f"device path {name}: {nd} grazing disagreements of {n} cast pairs")
+    vplg.vplset_release(ctx, vid)
+    vplg.scene_release(ctx, sid)
 
 
 GEN_VARIANTS = [("cornell", {}), ("room20k", {}), ("room200k", {}), ("cornell", {"walk_near": 1}),

@@ -1,10 +1,14 @@
-"""Render server: continuous admission under an HBM budget; every result equals the same request run alone."""
+"""Render server: continuous admission under an HBM budget; every result equals the same request run alone,
+and that lone run meets the oracle under the gather's parity protocol (tests/oracle_check.py), so the served
+image does too."""
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import oracle as orc  # noqa: E402
 from paper_2203_11484_amd import scenes  # noqa: E402
+from tests import oracle_check as OC  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -40,13 +44,21 @@ def _requests(scs, n, seed):
     return out
 
 
-def _alone(vplg, ctx, sid, cam, prm):
+def _alone(vplg, ctx, sid, cam, prm, oracle=None):
+    """The request run alone through the plain calls.  With oracle = (scene dict, pixels, label), its image is
+    also checked against the oracle on the G-buffer and VPL set this run made."""
     gb = vplg.GBuffer(cam["width"], cam["height"])
     vplg.gbuffer_render(ctx, sid, cam, gb)
     vid = vplg.vpls_generate(ctx, sid, cam, prm)
     rad = torch.zeros((3, cam["height"], cam["width"]), dtype=torch.float32, device="cuda")
     vplg.gather(ctx, sid, vid, gb, rad, prm)
     torch.cuda.synchronize()
+    if oracle is not None:
+        sc, pixels, label = oracle
+        L = rad.cpu().numpy().reshape(3, -1).T
+        nd, n = OC.check_gather(vplg, ctx, orc.Scene.from_dict(sc), sid, vid, gb, L, pixels, prm, label,
+                                min_lit=0.1)
+        print(f"{label}: {nd} grazing disagreements of {n} cast pairs", flush=True)
     vplg.vplset_release(ctx, vid)
     return rad
 
@@ -75,8 +87,14 @@ def test_server_results_equal_alone(env, budget_mb, inflight):
         assert st["peak_running"] >= 2, "requests should overlap on the device"
     for t in times:
         assert t["state"] == vplg.REQ_DONE and t["submit_ns"] <= t["admit_ns"] <= t["done_ns"]
-    for (si, cam, prm), rad in zip(reqs, outs):
-        assert torch.equal(rad, _alone(vplg, ctx, sids[si], cam, prm))
+    # the largest request of the mix is also held to the oracle, every pixel
+    big = max(range(len(reqs)), key=lambda i: reqs[i][1]["width"] * reqs[i][1]["height"] *
+              (reqs[i][2]["k_near"] + reqs[i][2]["n_far"]))
+    for i, ((si, cam, prm), rad) in enumerate(zip(reqs, outs)):
+        orq = None
+        if i == big:
+            orq = (scs[si], np.arange(cam["width"] * cam["height"]), f"served request {i} ({budget_mb} MB)")
+        assert torch.equal(rad, _alone(vplg, ctx, sids[si], cam, prm, orq))
 
 
 def test_server_large_view_equals_alone(env):
@@ -97,7 +115,8 @@ def test_server_large_view_equals_alone(env):
         assert vplg.server_wait(srv, t, timeout_ms=120000)["state"] == vplg.REQ_DONE
     finally:
         vplg.server_stop(srv)
-    alone = _alone(vplg, ctx, sids[0], cam, prm)
+    pixels = np.sort(np.random.default_rng(17).choice(512 * 512, 4096, replace=False))
+    alone = _alone(vplg, ctx, sids[0], cam, prm, (scs[0], pixels, "served 512x512 request"))
     assert (alone > 0).any()
     assert torch.equal(rad, alone)
 
