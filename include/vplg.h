@@ -231,10 +231,17 @@ int vplg_vplset_release(vplg_context* ctx, uint64_t vplset_id);
 
 /* g_clamp: C in min(C, cos_p cos_k / r^2) (> 0).  t_eps: shadow segments
  * x + s (y - x) test s in (t_eps, 1 - t_eps), both host triangles excluded.
- * tile_px: pixels per tile, 0 or 64 (8 x 8).  tile_vpl: waves sharing one
- * tile, each taking every tile_vpl-th VPL: 1, 2, 4, 8 or 16, or 0: the
- * autotuned choice for the view's shape, else 16 for a view of fewer than
- * 32 tiles per compute unit (it shortens the launch's tail) and 8 above. */
+ * The tile shape: tile_vpl = waves sharing one 8 x 8 pixel tile, each taking
+ * every tile_vpl-th VPL (1, 2, 4, 8 or 16); tile_px = pixels per work item,
+ * 64 (8 x 8), 128 (16 x 8) or 256 (16 x 16): a workgroup gathers the item's
+ * 8 x 8 tiles side by side, tile_vpl waves each, so tile_px / 64 * tile_vpl
+ * must be at most 16.  tile_vpl 0 leaves the shape open: the autotuned
+ * choice for the view's shape bucket, else 8 x 8 items with 16 waves per
+ * tile for a view of fewer than 32 tiles per compute unit (it shortens the
+ * launch's tail) and 8 above; a tile_px given with tile_vpl 0 fixes the
+ * pixel block (the waves are halved until it fits).  tile_px 0 = 64, or the
+ * tuned block when tile_vpl is 0.  A pixel's value depends on tile_vpl
+ * only, never on tile_px. */
 typedef struct {
     float g_clamp, t_eps;
     int32_t tile_px, tile_vpl;
@@ -246,13 +253,13 @@ typedef struct {
  * of width * height float32.  Float32 arithmetic, partial sums added in a
  * fixed order per pixel (deterministic: a pixel's value depends only on its
  * inputs and tile_vpl).
- * The launch is a resident grid whose workgroups claim 8 x 8 tiles from a
- * counter in work memory that the library keeps for `stream` (about 6 MB,
- * allocated on the stream's first gather, outside the context's budget;
- * the counter is reset by a kernel before each launch).  In a view of at
- * least four rounds of tiles (tiles >= 4 x resident workgroups) the last two
- * rounds are claimed in four parts each, whose sums a second kernel on the
- * stream adds up.  Gathers on one stream are ordered and may share the work memory;
+ * The launch is a resident grid whose workgroups claim pixel blocks (one
+ * work item of tile_px pixels each) from a counter in work memory that the
+ * library keeps for `stream` (about 6 MB, allocated on the stream's first
+ * gather, outside the context's budget; the counter is reset by a kernel
+ * before each launch).  In a view of at least four rounds of blocks
+ * (blocks >= 4 x resident workgroups) the last two rounds are claimed in
+ * four parts each, whose sums a second kernel on the stream adds up.  Gathers on one stream are ordered and may share the work memory;
  * gathers on different streams run concurrently.  A gather captured into a
  * HIP graph keeps the work memory of the stream it was captured on: capture
  * on a stream that has already run a gather (the first one allocates that
@@ -320,9 +327,10 @@ int vplg_direct(vplg_context* ctx, uint64_t scene_id, const vplg_gbuffer* gb, fl
 /* ------------------------------------------------------------------------ */
 
 /* One view of a batch: a resident scene and VPL set, its G-buffer, its
- * radiance planes and gather parameters (params.tile_vpl 0 = the autotuned
- * choice for the view's shape, else 8: a batch shares one tail, so the
- * tile-count rule of a lone gather does not apply). */
+ * radiance planes and gather parameters (params.tile_vpl 0 = the shape
+ * vplg_autotune_batch chose for the view's shape bucket, else 8 waves per
+ * 8 x 8 tile: a batch shares one tail, so the tile-count rule of a lone
+ * gather does not apply). */
 typedef struct {
     uint64_t scene_id, vplset_id;
     vplg_gbuffer gb;
@@ -331,31 +339,48 @@ typedef struct {
 } vplg_view;
 
 /* Gather n_views views of any scenes, resolutions and VPL counts in one
- * persistent launch (at most 4096 views).  Workgroups pull (view, tile group)
- * items from a device counter, most expensive views first.  The launch is a
+ * persistent launch (at most 4096 views).  Workgroups pull (view, pixel
+ * blocks) items from a device counter, most expensive views first.  The launch is a
  * HIP graph captured once per context and replayed; each call only rewrites
  * the device work table (copied from pinned host staging on `stream`) before
  * the replay.  Every view's radiance is identical to vplg_gather's with the
  * same resolved tile_vpl, whatever else is in the batch.  A batch that holds
- * a 16-wave view runs in 16-wave workgroups (a second graph, captured on
- * first use), else in 8-wave ones.  Every call shares the context's work
+ * a view whose pixel block takes more than 8 waves (tile_px / 64 * tile_vpl)
+ * runs in 16-wave workgroups (a second graph, captured on first use), else
+ * in 8-wave ones.  Every call shares the context's work
  * table, so calls are ordered on the device: a call's table copies wait (on
  * `stream`) for the previous call's replay, on whatever stream it ran.  The
  * host thread waits only for the previous call's table copy.  Calls on one
  * context from several host threads must be serialised by the caller. */
 int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views, void* stream);
 
-/* Time vplg_gather with tile_vpl 1, 2, 4, 8 and 16 on this view (synchronises
+/* Time vplg_gather on this view in every tile shape (tile_px 64, 128, 256 x
+ * tile_vpl 1 .. 16 with tile_px / 64 * tile_vpl <= 16; synchronises
  * `stream`), remember the fastest for the view's shape bucket
- * (ceil(log2(pixels)), ceil(log2(VPL capacity))) and return it.  Later
- * gathers with tile_vpl 0 in that bucket use it. */
+ * (ceil(log2(pixels)), ceil(log2(VPL capacity))) and return it.  Later lone
+ * gathers with tile_vpl 0 in that bucket use it.  The radiance planes are
+ * overwritten. */
 int vplg_autotune(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
-                  float* const radiance[3], const vplg_gather_params* p, void* stream, int32_t* best_tile_vpl);
-/* The tile_vpl a gather of this shape uses with tile_vpl 0 (the tile-count
- * rule of vplg_gather_params if untuned). */
-int vplg_autotune_lookup(vplg_context* ctx, int32_t width, int32_t height, int32_t n_vpls, int32_t* tile_vpl);
-/* Save / merge the autotuned table as text ("vplg-autotune 1", then lines
- * "log2_pixels log2_vpls tile_vpl").  load: ENOTFOUND if the file is absent. */
+                  float* const radiance[3], const vplg_gather_params* p, void* stream, int32_t* best_tile_vpl,
+                  int32_t* best_tile_px);
+/* Tune the views of a batch with the batched launch as the objective: the
+ * open views (tile_vpl 0 and tile_px 0) are grouped by shape bucket, and for
+ * each bucket (most pairs first) its views are gathered as a batch of their
+ * own in every tile shape (tile_px / 64 * tile_vpl <= 16), the first run
+ * untimed; the fastest shape per bucket is kept for views in batches.  Then
+ * the whole batch is timed (twice each) untuned and tuned, and the tuned
+ * shapes stay only if the batch runs faster with them (*n_tuned = buckets
+ * kept, else 0 and those buckets are left untuned).  Synchronises `stream`;
+ * overwrites the views' radiance planes. */
+int vplg_autotune_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views, void* stream, int32_t* n_tuned);
+/* The tile shape a gather of this shape uses with tile_vpl 0: lone
+ * (batched 0) or inside a batch (batched 1); the defaults of
+ * vplg_gather_params and vplg_view if untuned. */
+int vplg_autotune_lookup(vplg_context* ctx, int32_t width, int32_t height, int32_t n_vpls, int32_t batched,
+                         int32_t* tile_vpl, int32_t* tile_px);
+/* Save / merge the autotuned tables as text ("vplg-autotune 2", then lines
+ * "batched log2_pixels log2_vpls tile_vpl tile_px").  load: ENOTFOUND if the
+ * file is absent, EINVAL for another format or a bad entry. */
 int vplg_autotune_save(vplg_context* ctx, const char* path);
 int vplg_autotune_load(vplg_context* ctx, const char* path);
 

@@ -32,7 +32,7 @@ constexpr int kGatherMaxWaves = 16;     // waves per gather workgroup (VPL slice
 constexpr int kGatherMaxThreads = 64 * kGatherMaxWaves;
 constexpr int kChunk = 16;              // VPLs per first-level partial sum of a wave
 constexpr int kGroups = 4;              // round groups of a tile (the split granularity of the tail)
-constexpr int kSplitRounds = 2;         // split tiles per workgroup of the launch
+constexpr int kSplitRounds = 2;         // split blocks per workgroup of the launch
 constexpr float kInvPi = 0.318309886183790671538f;
 
 // Work memory of the allocation-free gather: the tile counter in the first
@@ -597,6 +597,27 @@ __device__ __forceinline__ void tile_out(const GatherArgs& a, int tile, int lane
     a.out[2][p] = active ? a.gb.alb[2][p] * s * S.z : 0.f;
 }
 
+// Pixel blocks of a view: G = 1, 2 or 4 tiles of 8 x 8 pixels (1 x 1, 2 x 1 or
+// 2 x 2 tiles), row-major over the view's block grid.
+__host__ __device__ __forceinline__ int block_cols(int G) { return G == 1 ? 1 : 2; }
+__host__ __device__ __forceinline__ int block_rows(int G) { return G == 4 ? 2 : 1; }
+__host__ __device__ __forceinline__ int view_blocks(int W, int H, int G)
+{
+    const int tx = (W + 7) >> 3, ty = (H + 7) >> 3;
+    return ((tx + block_cols(G) - 1) / block_cols(G)) * ((ty + block_rows(G) - 1) / block_rows(G));
+}
+
+// Tile (row-major index over the view's 8 x 8 tiles) of sub-tile i of block
+// b, or -1 where the block hangs over the view's edge.
+__device__ __forceinline__ int block_tile(int b, int i, int G, int W, int H)
+{
+    const int tx_n = (W + 7) >> 3, ty_n = (H + 7) >> 3;
+    const int bw = block_cols(G), bh = block_rows(G);
+    const int bx_n = (tx_n + bw - 1) / bw;
+    const int tx = (b % bx_n) * bw + i % bw, ty = (b / bx_n) * bh + i / bw;
+    return tx < tx_n && ty < ty_n ? ty * tx_n + tx : -1;
+}
+
 template <bool COUNT>
 __device__ __forceinline__ void flush_counters(unsigned long long* out, const Counters& cnt, unsigned long long pairs,
                                                int lane)
@@ -616,28 +637,31 @@ struct BlockSync {
     __device__ void operator()() const { __syncthreads(); }
 };
 
-// Persistent gather of one view: each workgroup of w waves (one VPL slice
-// each) claims work items from a device counter until none is left, so the
-// tiles' uneven costs spread over all CUs of all XCDs (a fixed tile per
-// workgroup leaves whole XCDs idle: the hardware deals workgroups to the XCDs
-// round robin, whatever their cost).  Items [0, split_full) are whole tiles;
-// the last split_count tiles are claimed as kGroups items of one round group
-// each, so the launch ends on items a kGroups-th of a tile long instead of
-// idling behind its last whole tiles (on a 512 x 512 view of 4,096 VPLs the
-// launch takes 5% less time).  A split item stores its group sum in
-// split_part; k_gather_split_finish (the next kernel on the stream) adds a
-// tile's group sums in group order -- the whole tile's own order, so a split
-// tile's result is bit for bit the unsplit one.  No workgroup waits for
-// another, and every workgroup reaches the exit.
+// Persistent gather of one view: each workgroup (G tile groups of w waves,
+// one VPL slice each) claims work items from a device counter until none is
+// left, so the tiles' uneven costs spread over all CUs of all XCDs (a fixed
+// tile per workgroup leaves whole XCDs idle: the hardware deals workgroups to
+// the XCDs round robin, whatever their cost).  An item is a pixel block of G
+// tiles, each gathered by its own group.  Items [0, split_full) are whole
+// blocks; the last split_count blocks are claimed as kGroups items of one
+// round group each, so the launch ends on items a kGroups-th of a block long
+// instead of idling behind its last whole blocks (on a 512 x 512 view of
+// 4,096 VPLs the launch takes 5% less time).  A split item stores each of its
+// tiles' group sums in split_part; k_gather_split_finish (the next kernel on
+// the stream) adds a tile's group sums in group order -- the whole tile's own
+// order, so a split tile's result is bit for bit the unsplit one.  No
+// workgroup waits for another, and every workgroup reaches the exit.
 template <bool COUNT>
 __device__ __forceinline__ void gather_persistent(const GatherArgs& a, unsigned int* __restrict__ counter)
 {
-    extern __shared__ float s_dyn[];  // kGroups * w slots of [3][64]
+    extern __shared__ float s_dyn[];  // kGroups * G * w slots of [3][64]
     float (*s_red)[3][64] = reinterpret_cast<float (*)[3][64]>(s_dyn);
     __shared__ int s_item;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
+    const int nw = a.waves_per_tile, G = a.px_tiles;
+    const int grp = wave / nw, wg = wave % nw;
+    const int W = a.gb.width, H = a.gb.height;
     const int full = a.split_full;
     const int total = full + a.split_count * kGroups;
     Counters cnt;
@@ -648,18 +672,25 @@ __device__ __forceinline__ void gather_persistent(const GatherArgs& a, unsigned 
         const int item = __builtin_amdgcn_readfirstlane(s_item);  // an LDS value is uniform here
         __syncthreads();
         if (item >= total) break;
-        // a whole tile, or split slot si: group si % kGroups of tile full + si / kGroups
+        // a whole block, or split slot si: round group si % kGroups of block full + si / kGroups
         const bool whole = item < full;
         const int si = whole ? 0 : item - full;
         const int g = si % kGroups;
-        const int tile = whole ? item : full + si / kGroups;
-        const float3 S = gather_tile<COUNT>(a, tile, whole ? 0 : g, whole ? kGroups : g + 1, wave, nw, lane, s_red, cnt,
+        const int blk = whole ? item : full + si / kGroups;
+        const int tile = block_tile(blk, grp, G, W, H);
+        float (*red)[3][64] = s_red + grp * kGroups * nw;
+        if (tile < 0) {  // every wave takes part in both barriers
+            __syncthreads();
+            __syncthreads();
+            continue;
+        }
+        const float3 S = gather_tile<COUNT>(a, tile, whole ? 0 : g, whole ? kGroups : g + 1, wg, nw, lane, red, cnt,
                                             pairs, BlockSync());
-        if (wave != 0) continue;
+        if (wg != 0) continue;
         if (whole) {
             tile_out(a, tile, lane, S);
         } else {
-            float* part = a.split_part + (size_t)si * 192;
+            float* part = a.split_part + ((size_t)(si / kGroups * G + grp) * kGroups + g) * 192;
             part[lane] = S.x;
             part[64 + lane] = S.y;
             part[128 + lane] = S.z;
@@ -681,11 +712,14 @@ __global__ __launch_bounds__(kGatherMaxThreads) void k_gather_counted(GatherArgs
     gather_persistent<true>(a, counter);
 }
 
-// One wave per split tile of the preceding gather: its group sums added in
-// group order, then the pixel's radiance.
+// One wave per tile of the split blocks of the preceding gather: its group
+// sums added in group order, then the pixel's radiance.
 __global__ __launch_bounds__(64) void k_gather_split_finish(GatherArgs a)
 {
     const int st = blockIdx.x, lane = threadIdx.x;
+    const int G = a.px_tiles;
+    const int tile = block_tile(a.split_full + st / G, st % G, G, a.gb.width, a.gb.height);
+    if (tile < 0) return;  // the whole wave: sub-tile over the view's edge
     const float* q = a.split_part + (size_t)st * kGroups * 192;
     float3 T = make_float3(0.f, 0.f, 0.f);
     for (int h = 0; h < kGroups; ++h) {
@@ -693,13 +727,14 @@ __global__ __launch_bounds__(64) void k_gather_split_finish(GatherArgs a)
         T.y += q[h * 192 + 64 + lane];
         T.z += q[h * 192 + 128 + lane];
     }
-    tile_out(a, a.split_full + st, lane, T);
+    tile_out(a, tile, lane, T);
 }
 
 // Persistent gather over many views.  Each workgroup of BW waves claims
 // work items from a device counter until none is left (every workgroup
-// reaches the exit).  Item i of view v covers tiles [j * g, (j + 1) * g)
-// with g = BW / w_v tile groups of w_v waves.
+// reaches the exit).  The workgroup holds g = BW / w_v tile groups of w_v
+// waves; item j of view v covers its pixel blocks [j * g / G, (j + 1) * g / G)
+// of G tiles each (group i takes sub-tile i % G of block j * g / G + i / G).
 template <int BW>
 __global__ __launch_bounds__(64 * BW) __attribute__((amdgpu_waves_per_eu(8))) void k_gather_batch(
     const BatchTable* __restrict__ tab, const GatherArgs* __restrict__ views, unsigned int* __restrict__ counter)
@@ -727,10 +762,12 @@ __global__ __launch_bounds__(64 * BW) __attribute__((amdgpu_waves_per_eu(8))) vo
         const int w = tab->waves[lo];
         const int groups = BW / w;
         const int group = wave / w;
-        const int tiles = ((a.gb.width + 7) >> 3) * ((a.gb.height + 7) >> 3);
-        const int tile = (item - tab->prefix[lo]) * groups + group;
-        // every wave takes part in both barriers, including groups past the last tile
-        const int t = tile < tiles ? tile : -1;
+        const int G = a.px_tiles;
+        const int blk = (item - tab->prefix[lo]) * (groups / G) + group / G;
+        // every wave takes part in both barriers, including groups past the last block
+        const int t = blk < view_blocks(a.gb.width, a.gb.height, G) ? block_tile(blk, group % G, G, a.gb.width,
+                                                                                  a.gb.height)
+                                                                      : -1;
         if (t >= 0) {
             const float3 S = gather_tile<false>(a, t, 0, kGroups, wave % w, w, lane, s_red + group * kGroups * w, cnt,
                                                 pairs, BlockSync());
@@ -937,6 +974,8 @@ hipError_t launch_pack_vpls(const DevVpls& v, hipStream_t s)
 // [3][64] floats per wave (a whole tile's group sums).
 static size_t gather_lds_bytes(int waves) { return (size_t)kGroups * waves * 3 * 64 * sizeof(float); }
 
+int gather_view_blocks(int width, int height, int px_tiles) { return view_blocks(width, height, px_tiles); }
+
 hipError_t gather_occupancy(int waves, bool counted, int* blocks_per_cu)
 {
     if (waves < 1 || waves > kGatherMaxWaves || (waves & (waves - 1))) return hipErrorInvalidValue;
@@ -990,19 +1029,21 @@ hipError_t launch_gather_scratch(const GatherArgs& a, void* scr, int blocks, hip
 
 hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counter, int blocks, hipStream_t s)
 {
-    const int tiles = ((a.gb.width + 7) / 8) * ((a.gb.height + 7) / 8);
-    const int waves = a.waves_per_tile;
+    const int G = a.px_tiles;
+    const int waves = a.waves_per_tile * G;
+    if (G != 1 && G != 2 && G != 4) return hipErrorInvalidValue;
     if (waves < 1 || waves > kGatherMaxWaves || (waves & (waves - 1)) || !counter || blocks < 1 ||
         a.split_cap < 0 || (a.split_cap > 0 && !a.split_part))
         return hipErrorInvalidValue;
-    const int nb = blocks < tiles ? blocks : tiles;
-    // the last kSplitRounds rounds of tiles (kSplitRounds per workgroup, at
-    // most split_cap) are claimed by round group, in views of at least
-    // 2 kSplitRounds rounds; smaller views keep whole tiles (they have no
-    // long tail, and quarter tiles would only add per-item work)
+    const int nblk = view_blocks(a.gb.width, a.gb.height, G);
+    const int nb = blocks < nblk ? blocks : nblk;
+    // the last kSplitRounds rounds of blocks (kSplitRounds per workgroup, at
+    // most split_cap tiles) are claimed by round group, in views of at least
+    // 2 kSplitRounds rounds; smaller views keep whole blocks (they have no
+    // long tail, and quarter blocks would only add per-item work)
     GatherArgs b = a;
-    b.split_count = tiles >= 2 * kSplitRounds * nb ? std::min(nb * kSplitRounds, a.split_cap) : 0;
-    b.split_full = tiles - b.split_count;
+    b.split_count = nblk >= 2 * kSplitRounds * nb ? std::min(nb * kSplitRounds, a.split_cap / G) : 0;
+    b.split_full = nblk - b.split_count;
     dim3 grid(nb), block(64 * waves);
     const size_t lds = gather_lds_bytes(waves);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
@@ -1010,7 +1051,7 @@ hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counte
         hipLaunchKernelGGL(k_gather_counted, grid, block, lds, s, b, counter);
     else
         hipLaunchKernelGGL(k_gather, grid, block, lds, s, b, counter);
-    if (b.split_count > 0) hipLaunchKernelGGL(k_gather_split_finish, dim3(b.split_count), dim3(64), 0, s, b);
+    if (b.split_count > 0) hipLaunchKernelGGL(k_gather_split_finish, dim3(b.split_count * G), dim3(64), 0, s, b);
     return hipGetLastError();
 }
 

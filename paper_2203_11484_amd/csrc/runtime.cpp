@@ -819,24 +819,31 @@ static uint32_t ceil_log2(long long x)
     return k;
 }
 
-// View-shape bucket of the autotuner: ceil(log2(pixels)), ceil(log2(VPLs)).
-static uint32_t shape_bucket(int width, int height, int n_vpls)
+uint32_t shape_bucket(int width, int height, int n_vpls)
 {
     return (ceil_log2((long long)width * height) << 8) | ceil_log2(n_vpls > 0 ? n_vpls : 1);
 }
 
-int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls, bool batched)
+TileShape tuned_shape(vplg_context* ctx, int width, int height, int n_vpls, bool batched)
 {
     // a server thread resolves tile shapes while the caller may autotune
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
-    auto it = ctx->tuned.find(shape_bucket(width, height, n_vpls));
-    if (it != ctx->tuned.end()) return it->second;
-    if (batched) return 8;
+    const auto& table = batched ? ctx->tuned_batch : ctx->tuned;
+    auto it = table.find(shape_bucket(width, height, n_vpls));
+    if (it != table.end()) return it->second;
+    TileShape t;
+    t.px_tiles = 1;
+    t.waves = 8;
+    if (batched) return t;
     if (ctx->cus == 0 && hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
         ctx->cus = 256;
     const long long tiles = (long long)((width + 7) / 8) * ((height + 7) / 8);
-    return tiles < (long long)kWideTilesPerCu * ctx->cus ? 16 : 8;
+    t.waves = tiles < (long long)kWideTilesPerCu * ctx->cus ? 16 : 8;
+    return t;
 }
+
+// px_tiles of a tile_px value (0 = 64), or 0 if it is not one of 0, 64, 128, 256
+static int px_tiles_of(int tile_px) { return tile_px == 0 || tile_px == 64 ? 1 : tile_px == 128 ? 2 : tile_px == 256 ? 4 : 0; }
 
 int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                   float* const radiance[3], const vplg_gather_params* p, GatherArgs* a, bool batched)
@@ -869,12 +876,24 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
     a->split_cap = 0;
     a->split_full = a->split_count = 0;
     a->split_part = nullptr;
-    // tile_vpl: waves (VPL slices) per 8 x 8 tile; 0 = the autotuned choice, else the tile-count rule
-    int w = p->tile_vpl == 0 ? tuned_waves(ctx, gb->width, gb->height, v->dev.capacity, batched) : p->tile_vpl;
+    // tile_vpl: waves (VPL slices) per 8 x 8 tile, tile_px: pixels per work item; tile_vpl 0 leaves the shape
+    // to the autotuned table (else the tile-count rule), with tile_px, if given, fixing the pixel block
+    int G = px_tiles_of(p->tile_px);
+    if (G == 0) return fail(VPLG_EINVAL, "tile_px must be 0, 64, 128 or 256 (got %d)", p->tile_px);
+    int w = p->tile_vpl;
+    if (w == 0) {
+        const TileShape t = tuned_shape(ctx, gb->width, gb->height, v->dev.capacity, batched);
+        w = t.waves;
+        if (p->tile_px == 0) G = t.px_tiles;
+        while (w > 1 && G * w > kGatherMaxWorkgroupWaves) w >>= 1;
+    }
     if (w < 1 || w > 16 || (w & (w - 1)))
         return fail(VPLG_EINVAL, "tile_vpl must be 0 or a power of two in [1, 16] (got %d)", p->tile_vpl);
-    if (p->tile_px != 0 && p->tile_px != 64) return fail(VPLG_EINVAL, "tile_px must be 0 or 64 (8 x 8 pixels)");
+    if (G * w > kGatherMaxWorkgroupWaves)
+        return fail(VPLG_EINVAL, "tile_px / 64 * tile_vpl must be at most %d (got %d * %d)", kGatherMaxWorkgroupWaves,
+                    G, w);
     a->waves_per_tile = w;
+    a->px_tiles = G;
     return VPLG_OK;
 }
 
@@ -911,7 +930,7 @@ int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t
             wk = it->second;
         }
     }
-    int rc = gather_grid(ctx, a.waves_per_tile, counted, &blocks);
+    int rc = gather_grid(ctx, a.waves_per_tile * a.px_tiles, counted, &blocks);
     if (rc) return rc;
     GatherArgs b = a;
     b.split_cap = split_tail ? kGatherSplitCap : 0;
@@ -943,7 +962,7 @@ int vplg_gather_noalloc(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id
     void* scr = gather_scratch_address(ctx->device);
     if (!scr) return fail(VPLG_EHIP, "device %d: the gather's scratch array has no address", ctx->device);
     int blocks = 0;
-    if ((rc = gather_grid(ctx, a.waves_per_tile, false, &blocks))) return rc;
+    if ((rc = gather_grid(ctx, a.waves_per_tile * a.px_tiles, false, &blocks))) return rc;
     // the launch splits at most gather_scratch_split_cap() tiles, whatever
     // the view's size; check the bound the array was sized for all the same
     const size_t need = 256 + sizeof(float) * (size_t)gather_scratch_split_cap() * gather_split_floats_per_tile();
@@ -1064,15 +1083,16 @@ int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views
         if ((rc = gather_common(ctx, vw.scene_id, vw.vplset_id, &vw.gb, vw.radiance, &vw.params, &args[v], true)))
             return fail(rc, "view %d: %s", v, g_err.c_str());
         waves[v] = args[v].waves_per_tile;
-        if (waves[v] > kBatchBlockWaves) wide = 1;
+        if (waves[v] * args[v].px_tiles > kBatchBlockWaves) wide = 1;
         cost[v] = (double)vw.gb.width * vw.gb.height * (double)args[v].vpls.capacity;
     }
-    // one workgroup size per launch: 16 waves when some view runs 16 per tile
+    // one workgroup size per launch: 16 waves when some view's pixel block
+    // needs more than 8 (its tiles times its waves per tile)
     const int bw = wide ? kBatchWideWaves : kBatchBlockWaves;
     for (int v = 0; v < n_views; ++v) {
-        const int tiles = ((views[v].gb.width + 7) / 8) * ((views[v].gb.height + 7) / 8);
-        const int groups = bw / waves[v];
-        items[v] = (tiles + groups - 1) / groups;
+        const int blocks = gather_view_blocks(views[v].gb.width, views[v].gb.height, args[v].px_tiles);
+        const int per_item = bw / waves[v] / args[v].px_tiles;  // blocks per workgroup item
+        items[v] = (blocks + per_item - 1) / per_item;
     }
     if ((rc = batch_init(ctx, wide))) return rc;
     BatchEngine& be = ctx->batch;
@@ -1105,43 +1125,48 @@ int vplg_gather_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views
 }
 
 int vplg_autotune(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
-                  float* const radiance[3], const vplg_gather_params* p, void* stream, int32_t* best_tile_vpl)
+                  float* const radiance[3], const vplg_gather_params* p, void* stream, int32_t* best_tile_vpl,
+                  int32_t* best_tile_px)
 {
-    if (!p || !best_tile_vpl) return fail(VPLG_EINVAL, "null argument");
+    if (!p || !best_tile_vpl || !best_tile_px) return fail(VPLG_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     float best_ms = 1e30f;
-    int best = 8;
+    TileShape best;
     int n_vpls = 0;
-    for (int w = 1; w <= kBatchWideWaves; w <<= 1) {
-        vplg_gather_params q = *p;
-        q.tile_vpl = w;
-        GatherArgs a;
-        int rc = gather_common(ctx, scene_id, vplset_id, gb, radiance, &q, &a);
-        if (rc) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return rc;
-        }
-        n_vpls = a.vpls.capacity;
-        float ms = 0.f;
-        rc = run_gather(ctx, a, false, s);  // warm
-        hipError_t e = hipSuccess;
-        if (!rc) e = hipEventRecord(e0, s);
-        if (!rc && e == hipSuccess) rc = run_gather(ctx, a, false, s);
-        if (!rc && e == hipSuccess) e = hipEventRecord(e1, s);
-        if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
-        if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (rc || e != hipSuccess) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return rc ? rc : fail(VPLG_EHIP, "autotune: %s", hipGetErrorString(e));
-        }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = w;
+    for (int G = 1; G <= 4; G <<= 1) {
+        for (int w = 1; G * w <= kGatherMaxWorkgroupWaves; w <<= 1) {
+            vplg_gather_params q = *p;
+            q.tile_vpl = w;
+            q.tile_px = 64 * G;
+            GatherArgs a;
+            int rc = gather_common(ctx, scene_id, vplset_id, gb, radiance, &q, &a);
+            if (rc) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return rc;
+            }
+            n_vpls = a.vpls.capacity;
+            float ms = 0.f;
+            rc = run_gather(ctx, a, false, s);  // warm
+            hipError_t e = hipSuccess;
+            if (!rc) e = hipEventRecord(e0, s);
+            if (!rc && e == hipSuccess) rc = run_gather(ctx, a, false, s);
+            if (!rc && e == hipSuccess) e = hipEventRecord(e1, s);
+            if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+            if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (rc || e != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return rc ? rc : fail(VPLG_EHIP, "autotune: %s", hipGetErrorString(e));
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best.waves = w;
+                best.px_tiles = G;
+            }
         }
     }
     (void)hipEventDestroy(e0);
@@ -1150,14 +1175,122 @@ int vplg_autotune(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, cons
         std::lock_guard<std::recursive_mutex> lock(ctx->mu);
         ctx->tuned[shape_bucket(gb->width, gb->height, n_vpls)] = best;
     }
-    *best_tile_vpl = best;
+    *best_tile_vpl = best.waves;
+    *best_tile_px = 64 * best.px_tiles;
     return VPLG_OK;
 }
 
-int vplg_autotune_lookup(vplg_context* ctx, int32_t width, int32_t height, int32_t n_vpls, int32_t* tile_vpl)
+// Time one batched launch of `views` on `s` (the caller has synchronised s).
+static int time_batch(vplg_context* ctx, const std::vector<vplg_view>& views, hipStream_t s, hipEvent_t e0,
+                      hipEvent_t e1, float* ms)
 {
-    if (!ctx || !tile_vpl) return fail(VPLG_EINVAL, "null argument");
-    *tile_vpl = tuned_waves(ctx, width, height, n_vpls, false);
+    HIPCHK(hipEventRecord(e0, s));
+    int rc = vplg_gather_batch(ctx, views.data(), (int32_t)views.size(), s);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    return VPLG_OK;
+}
+
+int vplg_autotune_batch(vplg_context* ctx, const vplg_view* views, int32_t n_views, void* stream, int32_t* n_tuned)
+{
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    if (n_views < 0 || n_views > kBatchMaxViews || (n_views > 0 && !views) || !n_tuned)
+        return fail(VPLG_EINVAL, "bad autotune_batch arguments");
+    *n_tuned = 0;
+    hipStream_t s = (hipStream_t)stream;
+    // the open views (tile_vpl 0, tile_px 0), by shape bucket; the rest stay as given
+    std::map<uint32_t, std::vector<int>> bucket;
+    std::map<uint32_t, double> bucket_cost;
+    for (int v = 0; v < n_views; ++v) {
+        GatherArgs a;
+        if ((rc = gather_common(ctx, views[v].scene_id, views[v].vplset_id, &views[v].gb, views[v].radiance,
+                                &views[v].params, &a, true)))
+            return fail(rc, "view %d: %s", v, g_err.c_str());
+        if (views[v].params.tile_vpl != 0 || views[v].params.tile_px != 0) continue;
+        const uint32_t k = shape_bucket(views[v].gb.width, views[v].gb.height, a.vpls.capacity);
+        bucket[k].push_back(v);
+        bucket_cost[k] += (double)views[v].gb.width * views[v].gb.height * (double)a.vpls.capacity;
+    }
+    std::vector<uint32_t> keys;
+    for (auto& kv : bucket) keys.push_back(kv.first);
+    std::stable_sort(keys.begin(), keys.end(), [&](uint32_t a, uint32_t b) { return bucket_cost[a] > bucket_cost[b]; });
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto done = [&](int code) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return code;
+    };
+    HIPCHK(hipStreamSynchronize(s));
+    std::map<uint32_t, TileShape> chosen;
+    for (uint32_t k : keys) {
+        // the bucket's views as a batch of their own, in each shape; the first
+        // run (untimed) warms the workgroup variants and the caches
+        float best_ms = 1e30f;
+        TileShape best;
+        bool warm = false;
+        for (int G = 1; G <= 4; G <<= 1) {
+            for (int w = 1; G * w <= kBatchWideWaves; w <<= 1) {
+                std::vector<vplg_view> sub;
+                for (int v : bucket[k]) {
+                    vplg_view x = views[v];
+                    x.params.tile_vpl = w;
+                    x.params.tile_px = 64 * G;
+                    sub.push_back(x);
+                }
+                float ms = 0.f;
+                if (!warm) {
+                    if ((rc = time_batch(ctx, sub, s, e0, e1, &ms))) return done(rc);
+                    warm = true;
+                }
+                if ((rc = time_batch(ctx, sub, s, e0, e1, &ms))) return done(rc);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best.waves = w;
+                    best.px_tiles = G;
+                }
+            }
+        }
+        chosen[k] = best;
+    }
+    // keep the tuned shapes only if the whole batch runs faster with them than untuned
+    std::map<uint32_t, TileShape> before;
+    {
+        std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+        before = ctx->tuned_batch;
+        for (uint32_t k : keys) ctx->tuned_batch.erase(k);
+    }
+    std::vector<vplg_view> all(views, views + n_views);
+    float ms_untuned = 0.f, ms_tuned = 0.f;
+    if ((rc = time_batch(ctx, all, s, e0, e1, &ms_untuned))) return done(rc);
+    if ((rc = time_batch(ctx, all, s, e0, e1, &ms_untuned))) return done(rc);
+    {
+        std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+        for (auto& kv : chosen) ctx->tuned_batch[kv.first] = kv.second;
+    }
+    if ((rc = time_batch(ctx, all, s, e0, e1, &ms_tuned))) return done(rc);
+    if ((rc = time_batch(ctx, all, s, e0, e1, &ms_tuned))) return done(rc);
+    if (ms_tuned > ms_untuned) {
+        std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+        ctx->tuned_batch = before;
+        for (uint32_t k : keys) ctx->tuned_batch.erase(k);
+    } else {
+        *n_tuned = (int32_t)chosen.size();
+    }
+    return done(VPLG_OK);
+}
+
+int vplg_autotune_lookup(vplg_context* ctx, int32_t width, int32_t height, int32_t n_vpls, int32_t batched,
+                         int32_t* tile_vpl, int32_t* tile_px)
+{
+    if (!ctx || !tile_vpl || !tile_px) return fail(VPLG_EINVAL, "null argument");
+    const TileShape t = tuned_shape(ctx, width, height, n_vpls, batched != 0);
+    *tile_vpl = t.waves;
+    *tile_px = 64 * t.px_tiles;
     return VPLG_OK;
 }
 
@@ -1166,10 +1299,13 @@ int vplg_autotune_save(vplg_context* ctx, const char* path)
     if (!ctx || !path) return fail(VPLG_EINVAL, "null argument");
     FILE* f = std::fopen(path, "w");
     if (!f) return fail(VPLG_EINVAL, "cannot write %s", path);
-    std::fprintf(f, "vplg-autotune 1\n");
+    std::fprintf(f, "vplg-autotune 2\n");
     {
         std::lock_guard<std::recursive_mutex> lock(ctx->mu);
-        for (auto& kv : ctx->tuned) std::fprintf(f, "%u %u %d\n", kv.first >> 8, kv.first & 0xff, kv.second);
+        for (int b = 0; b < 2; ++b)
+            for (auto& kv : b ? ctx->tuned_batch : ctx->tuned)
+                std::fprintf(f, "%d %u %u %d %d\n", b, kv.first >> 8, kv.first & 0xff, kv.second.waves,
+                             64 * kv.second.px_tiles);
     }
     std::fclose(f);
     return VPLG_OK;
@@ -1181,23 +1317,29 @@ int vplg_autotune_load(vplg_context* ctx, const char* path)
     FILE* f = std::fopen(path, "r");
     if (!f) return fail(VPLG_ENOTFOUND, "cannot read %s", path);
     int version = 0;
-    if (std::fscanf(f, "vplg-autotune %d", &version) != 1 || version != 1) {
+    if (std::fscanf(f, "vplg-autotune %d", &version) != 1 || version != 2) {
         std::fclose(f);
-        return fail(VPLG_EINVAL, "%s is not an autotune cache", path);
+        return fail(VPLG_EINVAL, "%s is not an autotune cache (version 2)", path);
     }
-    unsigned px, nv;
-    int w;
-    std::map<uint32_t, int> t;
-    while (std::fscanf(f, "%u %u %d", &px, &nv, &w) == 3) {
-        if (px > 63 || nv > 255 || w < 1 || w > kBatchWideWaves || (w & (w - 1))) {
+    int b, w, px;
+    unsigned lp, nv;
+    std::map<uint32_t, TileShape> t[2];
+    while (std::fscanf(f, "%d %u %u %d %d", &b, &lp, &nv, &w, &px) == 5) {
+        const int G = px_tiles_of(px);
+        if ((b != 0 && b != 1) || lp > 63 || nv > 255 || w < 1 || w > 16 || (w & (w - 1)) || px == 0 || G == 0 ||
+            G * w > (b ? kBatchWideWaves : kGatherMaxWorkgroupWaves)) {
             std::fclose(f);
             return fail(VPLG_EINVAL, "bad autotune entry in %s", path);
         }
-        t[(px << 8) | nv] = w;
+        TileShape ts;
+        ts.waves = w;
+        ts.px_tiles = G;
+        t[b][(lp << 8) | nv] = ts;
     }
     std::fclose(f);
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
-    for (auto& kv : t) ctx->tuned[kv.first] = kv.second;
+    for (auto& kv : t[0]) ctx->tuned[kv.first] = kv.second;
+    for (auto& kv : t[1]) ctx->tuned_batch[kv.first] = kv.second;
     return VPLG_OK;
 }
 

@@ -91,9 +91,17 @@ namespace rt {
 // Per-stream work memory of the single-view gather: its tile counter and the
 // round-group sums of up to kGatherSplitCap split tiles.
 constexpr int kGatherSplitCap = 2048;
+// waves of a single-view gather workgroup at most (tiles per block x waves per tile)
+constexpr int kGatherMaxWorkgroupWaves = 16;
 struct GatherWork {
     unsigned int* counter = nullptr;
     float* part = nullptr;
+};
+// Tile shape of a gather: waves per 8 x 8 tile (the VPL slices whose partial
+// sums fix a pixel's summation order) and 8 x 8 tiles per work item (its
+// pixel block: 1, 2 or 4, gathered side by side in one workgroup).
+struct TileShape {
+    int waves = 8, px_tiles = 1;
 };
 }  // namespace rt
 }  // namespace vplg
@@ -105,12 +113,14 @@ struct vplg_context {
     std::map<uint64_t, vplg::rt::SceneObj*> scenes;
     std::map<uint64_t, vplg::rt::VplSetObj*> sets;
     vplg::rt::BatchEngine batch;
-    std::map<uint32_t, int> tuned;  // view-shape bucket -> waves per 8 x 8 tile
+    // view-shape bucket -> tuned tile shape, for lone gathers and for views
+    // inside a batch (tuned with the batched launch as the objective)
+    std::map<uint32_t, vplg::rt::TileShape> tuned, tuned_batch;
     // work memory of the persistent single-view gather, per stream (launches
     // on one stream are ordered, so they may share it)
     std::map<void*, vplg::rt::GatherWork> stream_work;
     int cus = 0;                      // compute units of the device
-    int gather_blocks[2][5] = {};     // [counted][log2 waves]: resident workgroups per CU, 0 = not queried
+    int gather_blocks[2][5] = {};     // [counted][log2 workgroup waves]: resident workgroups per CU, 0 = not queried
     std::recursive_mutex mu;        // budget accounting, shared with a running server thread
 };
 
@@ -149,12 +159,15 @@ int alloc_genset(vplg_context* ctx, SceneObj* so, uint64_t scene_id, PatchIndex*
                  VplSetObj** out);
 int launch_genset(SceneObj* so, VplSetObj* v, const vplg_camera* cam, const vplg_gen_params* p, hipStream_t s);
 constexpr int kWideTilesPerCu = 32;
-// waves per 8 x 8 tile for a view: the autotuned choice for its shape, else,
-// for a view launched alone, 16 when it has fewer than kWideTilesPerCu tiles
-// per CU (shorter work items shorten the launch's tail) and 8 above; a view in
-// a batch gets 8 (the batch shares one tail, and 16-wave workgroups would tie
-// the 8-wave views' tile pairs to common barriers)
-int tuned_waves(vplg_context* ctx, int width, int height, int n_vpls, bool batched);
+// view-shape bucket of the autotuner: ceil(log2(pixels)) << 8 | ceil(log2(VPLs))
+uint32_t shape_bucket(int width, int height, int n_vpls);
+// tile shape of a view whose parameters leave it open (tile_vpl 0): the
+// autotuned choice for its shape (lone or batched table), else 8 x 8 pixel
+// blocks with, for a view launched alone, 16 waves per tile when it has fewer
+// than kWideTilesPerCu tiles per CU (shorter work items shorten the launch's
+// tail) and 8 above; a view in a batch gets 8 (the batch shares one tail, and
+// 16-wave workgroups would tie the 8-wave views' tile pairs to common barriers)
+TileShape tuned_shape(vplg_context* ctx, int width, int height, int n_vpls, bool batched);
 int gather_common(vplg_context* ctx, uint64_t scene_id, uint64_t vplset_id, const vplg_gbuffer* gb,
                   float* const radiance[3], const vplg_gather_params* p, GatherArgs* a, bool batched = false);
 int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffer* gb, float* const radiance[3],
@@ -163,7 +176,7 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
 // split_tail = false: whole tiles only (for gathers that share the GPU with
 // others, where no one view's tail leaves it idle); the result is the same.
 int run_gather(vplg_context* ctx, const GatherArgs& a, bool counted, hipStream_t s, bool split_tail = true);
-// resident workgroups of the single-view gather for `waves` waves per tile (cached per context)
+// resident workgroups of the single-view gather for workgroups of `waves` waves (cached per context)
 int gather_grid(vplg_context* ctx, int waves, bool counted, int* blocks);
 
 }  // namespace rt

@@ -95,11 +95,16 @@ struct GatherArgs {
     float g_clamp;
     float t_eps;
     int waves_per_tile;            // VPL slices per 8 x 8 pixel tile: 1, 2, 4, 8 or 16
+    // 8 x 8 tiles per work item (its pixel block): 1 (8 x 8), 2 (16 x 8) or
+    // 4 (16 x 16); px_tiles * waves_per_tile <= 16.  A block's tiles are
+    // gathered side by side, each by its own group of waves_per_tile waves,
+    // so a pixel's sum depends on waves_per_tile only.
+    int px_tiles;
     unsigned long long* counters;  // instrumented variant only
     // single-view gather only: split_part holds [split_cap][kGroups][3][64]
     // floats of work memory (split_cap 0: no tile is split); the launcher sets
-    // split_full (whole tiles claimed first) and split_count (tiles after it,
-    // claimed by round group)
+    // split_full (whole blocks claimed first) and split_count (blocks after
+    // it, claimed by round group; split_cap bounds split_count * px_tiles)
     int split_cap;
     int split_full, split_count;
     float* split_part;
@@ -107,7 +112,7 @@ struct GatherArgs {
 
 // Work table of a batched gather: views sorted by the caller, prefix[v] =
 // first work item of view v (prefix[n_views] = total), waves[v] = waves per
-// tile of view v (1, 2, 4 or 8).
+// tile of view v (1, 2, 4, 8 or 16; the view's px_tiles is in its args).
 constexpr int kBatchBlockWaves = 8;   // waves per persistent batch workgroup (views of <= 8 waves per tile)
 constexpr int kBatchWideWaves = 16;   // the wide variant, used when a batch holds a 16-wave view
 constexpr int kBatchMaxViews = 4096;
@@ -211,8 +216,10 @@ struct GenBuffers {
 // Persistent single-view gather: resets `counter` (a device word private to
 // stream `s`) and launches `blocks` workgroups that claim tiles from it.
 hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counter, int blocks, hipStream_t s);
-// Resident workgroups per CU of the single-view gather for `waves` waves per tile.
+// Resident workgroups per CU of the single-view gather for workgroups of `waves` waves.
 hipError_t gather_occupancy(int waves, bool counted, int* blocks_per_cu);
+// Pixel blocks of px_tiles 8 x 8 tiles (1, 2 or 4) covering a view.
+int gather_view_blocks(int width, int height, int px_tiles);
 // Floats of split-tile work memory per tile (its round groups' sums).
 int gather_split_floats_per_tile();
 // Allocation-free gather: its work memory is a fixed device array of the

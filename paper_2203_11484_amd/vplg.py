@@ -124,8 +124,10 @@ _SIGS = {
     "vplg_direct": (C.c_int, [_p, _u64, C.POINTER(GBufferStruct), C.POINTER(_p), C.c_float, _p]),
     "vplg_gather_batch": (C.c_int, [_p, C.POINTER(View), C.c_int32, _p]),
     "vplg_autotune": (C.c_int, [_p, _u64, _u64, C.POINTER(GBufferStruct), C.POINTER(_p), C.POINTER(GatherParams), _p,
-                                C.POINTER(C.c_int32)]),
-    "vplg_autotune_lookup": (C.c_int, [_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
+                                C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "vplg_autotune_batch": (C.c_int, [_p, C.POINTER(View), C.c_int32, _p, C.POINTER(C.c_int32)]),
+    "vplg_autotune_lookup": (C.c_int, [_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]),
     "vplg_autotune_save": (C.c_int, [_p, C.c_char_p]),
     "vplg_autotune_load": (C.c_int, [_p, C.c_char_p]),
     "vplg_server_start": (C.c_int, [_p, C.POINTER(ServerParams), C.POINTER(_p)]),
@@ -451,17 +453,28 @@ def gather_batch(ctx, views, stream=None):
 
 
 def autotune(ctx, scene_id, vplset_id, gb, radiance, params=None, stream=None):
+    """Returns the fastest (tile_vpl, tile_px) of a lone gather of this view, now the tuned shape of its bucket."""
     gp = params if isinstance(params, GatherParams) else make_gather_params(params)
-    best = C.c_int32()
+    best, px = C.c_int32(), C.c_int32()
     _check(lib().vplg_autotune(ctx, scene_id, vplset_id, C.byref(gb.struct), radiance_planes(radiance), C.byref(gp),
-                               _stream(stream), C.byref(best)))
-    return best.value
+                               _stream(stream), C.byref(best), C.byref(px)))
+    return best.value, px.value
 
 
-def autotune_lookup(ctx, width, height, n_vpls):
-    w = C.c_int32()
-    _check(lib().vplg_autotune_lookup(ctx, int(width), int(height), int(n_vpls), C.byref(w)))
-    return w.value
+def autotune_batch(ctx, views, stream=None):
+    """Tune the open views' shape buckets with the batched launch as the objective; returns the buckets kept."""
+    arr = make_views(views)
+    n = C.c_int32()
+    _check(lib().vplg_autotune_batch(ctx, arr, len(views), _stream(stream), C.byref(n)))
+    return n.value
+
+
+def autotune_lookup(ctx, width, height, n_vpls, batched=False):
+    """(tile_vpl, tile_px) a gather of this shape takes with tile_vpl 0."""
+    w, px = C.c_int32(), C.c_int32()
+    _check(lib().vplg_autotune_lookup(ctx, int(width), int(height), int(n_vpls), int(bool(batched)), C.byref(w),
+                                      C.byref(px)))
+    return w.value, px.value
 
 
 def autotune_save(ctx, path):

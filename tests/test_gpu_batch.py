@@ -31,16 +31,17 @@ def ctx(vplg):
 
 def _views(vplg, ctx):
     """Seven views over two scenes: ragged sizes, different VPL budgets and tile shapes (1 to 16 waves per
-    tile, so the batch runs in 16-wave workgroups; a subset without a 16-wave view runs in 8-wave ones)."""
+    tile, pixel blocks of 1, 2 and 4 tiles, so the batch runs in 16-wave workgroups; a subset whose blocks
+    take at most 8 waves runs in 8-wave ones)."""
     sc_a = scenes.make_scene("cornell")
     sc_b = scenes.procedural_room(11, 6, 6, 2, 2, k_near=192, n_far=320, d_near=7.0)
     ids = {}
     for key, sc in (("a", sc_a), ("b", sc_b)):
         ids[key] = (sc, vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"]))
-    specs = [("a", 40, 36, 1), ("b", 64, 64, 8), ("a", 100, 75, 4), ("b", 72, 40, 2), ("b", 33, 17, 8),
-             ("a", 128, 96, 0), ("b", 56, 48, 16)]
+    specs = [("a", 40, 36, 1, 256), ("b", 64, 64, 8, 64), ("a", 100, 75, 4, 128), ("b", 72, 40, 2, 256),
+             ("b", 33, 17, 8, 0), ("a", 128, 96, 0, 0), ("b", 56, 48, 16, 0)]
     views = []
-    for key, w, h, tv in specs:
+    for key, w, h, tv, px in specs:
         sc, sid = ids[key]
         cam = dict(sc["camera"])
         cam["width"], cam["height"] = w, h
@@ -50,6 +51,7 @@ def _views(vplg, ctx):
         rad = torch.full((3, h, w), -1.0, dtype=torch.float32, device="cuda")
         gp = vplg.make_gather_params(sc["params"])
         gp.tile_vpl = tv
+        gp.tile_px = px
         views.append(dict(scene=sid, vplset=vid, gb=gb, radiance=rad, params=gp, sc=sc, cam=cam))
     return views
 
@@ -61,6 +63,7 @@ def test_batch_equals_per_view_and_replays(vplg, ctx):
         # tile_vpl 0 resolves to 8 in a batch (untuned); a lone gather's rule would pick 16 for these sizes
         gp = vplg.make_gather_params(v["sc"]["params"])
         gp.tile_vpl = v["params"].tile_vpl or 8
+        gp.tile_px = v["params"].tile_px
         r = torch.zeros_like(v["radiance"])
         vplg.gather(ctx, v["scene"], v["vplset"], v["gb"], r, gp)
         refs.append(r)
@@ -74,8 +77,8 @@ def test_batch_equals_per_view_and_replays(vplg, ctx):
             assert torch.equal(v["radiance"], refs[i]), f"replay {rep}: view {i} differs from its single gather"
         # eager work between replays
         _ = (torch.ones(1 << 20, device="cuda") * 2).sum().item()
-    # a different subset and order in the next replay
-    sub = [views[4], views[0], views[2]]
+    # a different subset and order in the next replay (blocks of at most 8 waves: 8-wave workgroups)
+    sub = [views[4], views[0], views[3]]
     for v in sub:
         v["radiance"].fill_(-1.0)
     vplg.gather_batch(ctx, sub)
@@ -109,6 +112,37 @@ def test_split_tail_equals_whole_tiles(vplg, ctx, size, tile_vpl):
     torch.cuda.synchronize()
     assert (lone >= 0).all() and (lone > 0).any()
     assert torch.equal(view["radiance"], lone)
+    vplg.vplset_release(ctx, vid)
+    vplg.scene_release(ctx, sid)
+
+
+@pytest.mark.parametrize("size", [(512, 512), (100, 75)])
+def test_pixel_blocks_equal_single_tiles(vplg, ctx, size):
+    """Every tile shape of a lone gather: pixel blocks of 2 (16 x 8) and 4 (16 x 16) tiles give, bit for bit,
+    the single-tile result at the same waves per tile, with (512 x 512: at least four rounds of blocks) and
+    without (100 x 75, ragged: blocks hang over the edges) the split tail; and so does the batch."""
+    w, h = size
+    sc = scenes.make_scene("cornell", width=w, height=h)
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
+    gb = vplg.GBuffer(w, h)
+    vplg.gbuffer_render(ctx, sid, sc["camera"], gb)
+    vid = vplg.vpls_generate(ctx, sid, sc["camera"], sc["params"])
+    for tv in (1, 2, 4, 8):
+        outs = {}
+        for px in (64, 128, 256):
+            if px // 64 * tv > 16:
+                continue
+            gp = vplg.make_gather_params(sc["params"])
+            gp.tile_vpl, gp.tile_px = tv, px
+            outs[px] = torch.full((3, h, w), -1.0, dtype=torch.float32, device="cuda")
+            vplg.gather(ctx, sid, vid, gb, outs[px], gp)
+            view = dict(scene=sid, vplset=vid, gb=gb, radiance=torch.full_like(outs[px], -1.0), params=gp)
+            vplg.gather_batch(ctx, [view])
+            torch.cuda.synchronize()
+            assert torch.equal(view["radiance"], outs[px]), f"tile_vpl {tv} tile_px {px}: batch != lone"
+        assert (outs[64] >= 0).all() and (outs[64] > 0).any()
+        for px, o in outs.items():
+            assert torch.equal(o, outs[64]), f"tile_vpl {tv}: tile_px {px} differs from 64"
     vplg.vplset_release(ctx, vid)
     vplg.scene_release(ctx, sid)
 
@@ -229,31 +263,78 @@ def test_batch_rejects_bad_views(vplg, ctx):
     with pytest.raises(vplg.VplgError) as e:
         vplg.gather_batch(ctx, [views[0], bad])
     assert e.value.code == vplg.ENOTFOUND
-    gp = vplg.make_gather_params()
-    gp.tile_vpl = 3
-    big = dict(views[0])
-    big["params"] = gp
-    with pytest.raises(vplg.VplgError) as e:
-        vplg.gather_batch(ctx, [big])
-    assert e.value.code == vplg.EINVAL
+    for tv, px in ((3, 0), (2, 96), (8, 256), (16, 128)):
+        gp = vplg.make_gather_params()
+        gp.tile_vpl, gp.tile_px = tv, px
+        big = dict(views[0])
+        big["params"] = gp
+        with pytest.raises(vplg.VplgError) as e:
+            vplg.gather_batch(ctx, [big])
+        assert e.value.code == vplg.EINVAL, (tv, px)
+        with pytest.raises(vplg.VplgError) as e:
+            vplg.gather(ctx, big["scene"], big["vplset"], big["gb"], big["radiance"], gp)
+        assert e.value.code == vplg.EINVAL, (tv, px)
 
 
 def test_autotune_roundtrip(vplg, ctx, tmp_path):
     v = _views(vplg, ctx)[1]
     best = vplg.autotune(ctx, v["scene"], v["vplset"], v["gb"], v["radiance"], v["params"])
-    assert best in (1, 2, 4, 8, 16)
+    assert best[0] in (1, 2, 4, 8, 16) and best[1] in (64, 128, 256) and best[1] // 64 * best[0] <= 16
     n = vplg.vplset_count(ctx, v["vplset"])
     assert vplg.autotune_lookup(ctx, v["gb"].width, v["gb"].height, n) == best
     path = os.path.join(tmp_path, "tune.txt")
     vplg.autotune_save(ctx, path)
     c2 = vplg.context_create(0)
     try:
-        # untuned: the tile-count rule (16 waves below 32 tiles per compute unit, else 8)
+        # untuned: 8 x 8 blocks and the tile-count rule (16 waves below 32 tiles per compute unit, else 8);
+        # in a batch, 8
         tiles = ((v["gb"].width + 7) // 8) * ((v["gb"].height + 7) // 8)
         cus = torch.cuda.get_device_properties(0).multi_processor_count
-        assert vplg.autotune_lookup(c2, v["gb"].width, v["gb"].height, n) == (16 if tiles < 32 * cus else 8)
-        assert vplg.autotune_lookup(c2, 1920, 1080, n) == (16 if 240 * 135 < 32 * cus else 8)
+        assert vplg.autotune_lookup(c2, v["gb"].width, v["gb"].height, n) == (16 if tiles < 32 * cus else 8, 64)
+        assert vplg.autotune_lookup(c2, 1920, 1080, n) == (16 if 240 * 135 < 32 * cus else 8, 64)
+        assert vplg.autotune_lookup(c2, 1920, 1080, n, batched=True) == (8, 64)
         vplg.autotune_load(c2, path)
         assert vplg.autotune_lookup(c2, v["gb"].width, v["gb"].height, n) == best
+    finally:
+        vplg.context_destroy(c2)
+
+
+def test_autotune_batch(vplg, ctx, tmp_path):
+    """The batch autotuner on open views (tile shape left to it): each bucket's shape comes from timing that
+    bucket's views as a batch; the tuned shapes are kept only if the whole batch is faster with them.  Either
+    way every view then equals a lone gather at the shape the batch resolved for it, and the batched table
+    survives a save and load."""
+    views = _views(vplg, ctx)
+    for v in views:
+        v["params"] = vplg.make_gather_params(v["sc"]["params"])  # open: tile_vpl 0, tile_px 0
+    c = ctx  # the views' scenes and VPL sets live in this context
+    kept = vplg.autotune_batch(c, views)
+    assert 0 <= kept <= len(views)
+    for v in views:
+        v["radiance"].fill_(-1.0)
+    vplg.gather_batch(c, views)
+    torch.cuda.synchronize()
+    shapes = set()
+    for i, v in enumerate(views):
+        n = vplg.vplset_count(c, v["vplset"])
+        w, px = vplg.autotune_lookup(c, v["gb"].width, v["gb"].height, n, batched=True)
+        shapes.add((w, px))
+        assert px // 64 * w <= 16
+        gp = vplg.make_gather_params(v["sc"]["params"])
+        gp.tile_vpl, gp.tile_px = w, px
+        r = torch.zeros_like(v["radiance"])
+        vplg.gather(c, v["scene"], v["vplset"], v["gb"], r, gp)
+        torch.cuda.synchronize()
+        assert torch.equal(v["radiance"], r), f"view {i}"
+    print(f"batch autotuner kept {kept} buckets; shapes {sorted(shapes)}", flush=True)
+    path = os.path.join(tmp_path, "tune_batch.txt")
+    vplg.autotune_save(c, path)
+    c2 = vplg.context_create(0)
+    try:
+        vplg.autotune_load(c2, path)
+        for v in views:
+            n = vplg.vplset_count(c, v["vplset"])
+            assert (vplg.autotune_lookup(c2, v["gb"].width, v["gb"].height, n, batched=True) ==
+                    vplg.autotune_lookup(c, v["gb"].width, v["gb"].height, n, batched=True))
     finally:
         vplg.context_destroy(c2)
