@@ -256,8 +256,14 @@ bool build_bvh(const float* xyz, int T, std::vector<float4>& out_nodes, std::vec
         o[0] = make_float4(lo0[0], hi0[0], lo0[1], hi0[1]);
         o[1] = make_float4(lo1[0], hi1[0], lo1[1], hi1[1]);
         o[2] = make_float4(lo0[2], hi0[2], lo1[2], hi1[2]);
+        // the plane between the children along the split axis, as an
+        // order-preserving integer key (its two low bits carry the axis)
+        const float split = 0.5f * (hi0[axis] + lo1[axis]);
+        int sbits;
+        std::memcpy(&sbits, &split, sizeof sbits);
+        const int skey = sbits ^ ((sbits >> 31) & 0x7fffffff);
         float f[4];
-        int ints[4] = {c0, c1, k0 | (k1 << 16), axis};
+        int ints[4] = {c0, c1, k0 | (k1 << 16), (skey & ~3) | axis};
         std::memcpy(f, ints, sizeof f);
         o[3] = make_float4(f[0], f[1], f[2], f[3]);
     }

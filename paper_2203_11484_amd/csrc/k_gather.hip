@@ -329,11 +329,25 @@ __device__ __forceinline__ unsigned long long leaf_any_hit(const float4* __restr
     return alive;
 }
 
+// Order-preserving integer key of a float (as the node records store their
+// split positions): integer comparison of keys is float comparison.
+__device__ __forceinline__ int order_key(float f)
+{
+    const int b = __float_as_int(f);
+    return b ^ ((b >> 31) & 0x7fffffff);
+}
+
 // BVH walk of one packet (see packet_visible) with slab-test variant OCT.
+// Where the packet enters both children, it goes first to the one on the
+// side of the split holding the midpoint (keys mk) of its lead segment:
+// shadow rays are mostly blocked between their ends, away from the surfaces
+// they start and end on, so the middle first finds a blocker sooner (on the
+// 202k-triangle room a blocked packet took 49 node steps near side first
+// and takes about 32 this way).
 template <bool COUNT, int OCT>
 __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                          const SlabRay& r, const WtRay& wr, bool act, float tlo, float thi, int ex0,
-                                         int ex1, int oct, int lane, Counters& cnt)
+                                         int ex1, int mkx, int mky, int mkz, int lane, Counters& cnt)
 {
     unsigned long long alive = ballot(act);
     int slot = 0;
@@ -348,7 +362,7 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
         const Rec nd = load_rec(nodes, node);
         const float4 n0 = nd.q0, n1 = nd.q1, n2 = nd.q2, n3f = nd.q3;
         const int c0 = __float_as_int(n3f.x), c1 = __float_as_int(n3f.y);
-        const int kk = __float_as_int(n3f.z), axis = __float_as_int(n3f.w);
+        const int kk = __float_as_int(n3f.z), split = __float_as_int(n3f.w);
         if (COUNT) {
             if (lane_bit(entered & alive, lane)) cnt.nodes++;
             if (lane_bit(alive, lane)) cnt.rides++;
@@ -375,9 +389,11 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
         }
         if (b0) {
             if (b1) {
-                // both: the child on the near side of the split plane for
-                // the packet's direction signs first, the other pushed
-                const bool first1 = (oct >> axis) & 1;
+                // both: the child on the midpoint's side of the split first,
+                // the other pushed (uniform values: scalar compares)
+                const int axis = split & 3;
+                const int mk = axis == 0 ? mkx : (axis == 1 ? mky : mkz);
+                const bool first1 = mk > (split & ~3);
                 slot = lane == sp ? (first1 ? c0 : c1) : slot;
                 if (COUNT) {
                     const unsigned long long later = first1 ? b0 : b1;
@@ -447,20 +463,24 @@ __device__ __forceinline__ bool packet_visible(const DevScene& sc, float ox, flo
     const unsigned long long sx = ballot(r.ix < 0.f) & am, sy = ballot(r.iy < 0.f) & am, sz = ballot(r.iz < 0.f) & am;
     const bool uni = (sx == 0 || sx == am) && (sy == 0 || sy == am) && (sz == 0 || sz == am);
     const int oct = uni ? (sx ? 1 : 0) | (sy ? 2 : 0) | (sz ? 4 : 0) : 8;
-    // child order: the direction signs of the packet, or of its first active lane
+    // child order: the midpoint of the first active lane's segment
     const int lead = __builtin_ctzll(am | (1ull << 63));
-    const int ord = uni ? oct
-                        : (int)(((sx >> lead) & 1) | (((sy >> lead) & 1) << 1) | (((sz >> lead) & 1) << 2));
+    const int mkx = __builtin_amdgcn_readfirstlane(order_key(__int_as_float(__builtin_amdgcn_readlane(
+        __float_as_int(fmaf(0.5f, dx, ox)), lead))));
+    const int mky = __builtin_amdgcn_readfirstlane(order_key(__int_as_float(__builtin_amdgcn_readlane(
+        __float_as_int(fmaf(0.5f, dy, oy)), lead))));
+    const int mkz = __builtin_amdgcn_readfirstlane(order_key(__int_as_float(__builtin_amdgcn_readlane(
+        __float_as_int(fmaf(0.5f, dz, oz)), lead))));
     switch (oct) {
-    case 0: return traverse<COUNT, 0>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
-    case 1: return traverse<COUNT, 1>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
-    case 2: return traverse<COUNT, 2>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
-    case 3: return traverse<COUNT, 3>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
-    case 4: return traverse<COUNT, 4>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
-    case 5: return traverse<COUNT, 5>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
-    case 6: return traverse<COUNT, 6>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
-    case 7: return traverse<COUNT, 7>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
-    default: return traverse<COUNT, 8>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, ord, lane, cnt);
+    case 0: return traverse<COUNT, 0>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
+    case 1: return traverse<COUNT, 1>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
+    case 2: return traverse<COUNT, 2>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
+    case 3: return traverse<COUNT, 3>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
+    case 4: return traverse<COUNT, 4>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
+    case 5: return traverse<COUNT, 5>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
+    case 6: return traverse<COUNT, 6>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
+    case 7: return traverse<COUNT, 7>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
+    default: return traverse<COUNT, 8>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
     }
 }
 

@@ -16,12 +16,15 @@ namespace vplg {
 //   n0 = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
 //   n1 = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
 //   n2 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
-//   n3 = (int c0, int c1, int c0_count | c1_count << 16, int axis)
+//   n3 = (int c0, int c1, int c0_count | c1_count << 16, int split)
 // A child with count > 0 is a leaf holding triangles [c, c + count) of the
 // leaf-ordered triangle array; count == 0 is an inner node.  Both children
 // are always present (a scene that fits one leaf gets a root whose two
-// children are that leaf).  `axis` is the node's split axis: child 0 holds
-// the primitives with the lower centroids along it.  Node 0 is the root.
+// children are that leaf).  split & 3 is the node's split axis: child 0 holds
+// the primitives with the lower centroids along it; split & ~3 is the
+// position between the children along it, (c0.hi + c1.lo) / 2, as an
+// order-preserving integer key of its float bits (b ^ ((b >> 31) &
+// 0x7fffffff), two low bits dropped).  Node 0 is the root.
 //
 // Leaf-ordered triangles, four float4 each (one 64-byte scalar load):
 // (A, id), (B, cut), (C, 0), (n, 0) with id = the original triangle index
