@@ -27,7 +27,8 @@ def _ptr(a):
 def lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle.so")
+        # ORACLE_LIB: another build of oracle.c (the sanitizer test loads an ASan/UBSan one)
+        path = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
         if not os.path.exists(path):
             import importlib.util
             spec = importlib.util.spec_from_file_location("_oracle_build", os.path.join(_HERE, "build.py"))
