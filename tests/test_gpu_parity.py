@@ -287,3 +287,27 @@ def test_abi_errors(vplg, ctx):
             vplg.vpls_generate(ctx, sid, sc["camera"], dict(sc["params"], **bad))
         assert e.value.code == vplg.EINVAL, bad
     vplg.scene_release(ctx, sid)
+
+
+@pytest.mark.parametrize("name", ["cornell", "cornell_point", "room20k", "room200k"])
+def test_gather_equals_instrumented_walk(vplg, ctx, name):
+    """The gather and the instrumented gather (which counts each ray's own traversal) must give the same
+    image bit for bit at the workloads' full sizes on the device path: the counting must not change what is
+    computed, and any change to the gather's walk that keeps its answers exact keeps this equality."""
+    sc = scenes.make_scene(name)
+    cam, prm = sc["camera"], sc["params"]
+    sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
+    gb = vplg.GBuffer(cam["width"], cam["height"])
+    vplg.gbuffer_render(ctx, sid, cam, gb)
+    vid = vplg.vpls_generate(ctx, sid, cam, prm)
+    fast = torch.full((3, cam["height"], cam["width"]), -1.0, dtype=torch.float32, device="cuda")
+    walk = torch.full_like(fast, -2.0)
+    cnt = torch.zeros(vplg.N_COUNTERS, dtype=torch.int64, device="cuda")
+    vplg.gather(ctx, sid, vid, gb, fast, prm)
+    vplg.gather_counted(ctx, sid, vid, gb, walk, cnt, prm)
+    torch.cuda.synchronize()
+    assert (fast >= 0).all() and (fast > 0).any()
+    diff = (fast != walk).sum().item()
+    assert diff == 0, f"{name}: {diff} values differ between the gather and the instrumented walk"
+    vplg.vplset_release(ctx, vid)
+    vplg.scene_release(ctx, sid)
