@@ -32,15 +32,17 @@ FLOP_PAIR, FLOP_RAY, FLOP_NODE, FLOP_TRI = 27, 13, 24, 44
 
 def measured_traffic(workload):
     """HBM bytes per gather launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, scaled by
-    the same counters' reading of a 1 GiB copy; None unless the gather source is the one measured."""
+    the same counters' reading of a 1 GiB copy; None unless the gather source and the BVH builder (whose tree
+    the gather walks) are the ones measured."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_gather_{workload}_hbm.json")
-    src = os.path.join(ROOT, "paper_2203_11484_amd", "csrc", "k_gather.hip")
+    csrc = os.path.join(ROOT, "paper_2203_11484_amd", "csrc")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != d.get("kernel_source_sha256"):
-        return None
+    for name, key in (("k_gather.hip", "kernel_source_sha256"), ("bvh_build.cpp", "builder_source_sha256")):
+        if hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest() != d.get(key):
+            return None
     return d["traffic_bytes_per_launch"]
 
 

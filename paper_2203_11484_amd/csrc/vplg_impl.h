@@ -20,11 +20,11 @@ namespace vplg {
 // A child with count > 0 is a leaf holding triangles [c, c + count) of the
 // leaf-ordered triangle array; count == 0 is an inner node.  Both children
 // are always present (a scene that fits one leaf gets a root whose two
-// children are that leaf).  split & 3 is the node's split axis: child 0 holds
-// the primitives with the lower centroids along it; split & ~3 is the
-// position between the children along it, (c0.hi + c1.lo) / 2, as an
-// order-preserving integer key of its float bits (b ^ ((b >> 31) &
-// 0x7fffffff), two low bits dropped).  Node 0 is the root.
+// children are that leaf).  split & 3 is the node's split axis, the axis
+// along which the children's box centres lie farthest apart, child 0's the
+// lower; split & ~3 is the position between the children along it,
+// (c0.hi + c1.lo) / 2, as an order-preserving integer key of its float bits
+// (b ^ ((b >> 31) & 0x7fffffff), two low bits dropped).  Node 0 is the root.
 //
 // Leaf-ordered triangles, four float4 each (one 64-byte scalar load):
 // (A, id), (B, cut), (C, 0), (n, 0) with id = the original triangle index
