@@ -5,15 +5,19 @@ the VPL set are downloaded from the device, whoever made them (the oracle's own 
 G-buffer render and VPL generation, a served request's lone twin).  Then:
 
 * visibility: the GPU's bits (the gather's own shadow-ray code, through the visibility dump) against the
-  oracle's plain definition, pair by pair; every disagreement must be grazing (moving an endpoint by 1e-5
-  of the scene diagonal flips the oracle's answer) and, over the pairs whose shadow ray the gather casts,
-  at most 1e-4 of them;
+  oracle's plain definition, pair by pair; every disagreement must be grazing (moving an endpoint by BAND =
+  1e-7 of the scene diagonal along a coordinate axis flips the oracle's answer: 1.4e-6 in the rooms, about
+  one and a half FP32 ulps of their coordinates) and, over the pairs whose shadow ray the gather casts, at
+  most 1e-4 of them;
 * radiance: per channel within 1e-4 relative (floor 1e-3 of the channel mean, exact zeros stay zero), with
   the oracle re-evaluated on the GPU's bit for the disagreeing pairs.
 """
 import numpy as np
 
 from tests import helpers as H
+
+# grazing band of the visibility protocol, relative to the scene's bounding-box diagonal
+BAND = 1e-7
 
 
 def dump_visibility(vplg, ctx, sid, vid, gb, pixels, M, prm):
@@ -54,7 +58,11 @@ def check_gather(vplg, ctx, S, sid, vid, gb, L_gpu, pixels, prm, label, min_lit=
           f"cast pairs", flush=True)
     if len(dis[0]):
         xi, ki = dis
-        graz = S.grazing(gpos[xi], gtri[xi], vpos[ki], vtri[ki], eps=prm["t_eps"], delta_rel=1e-5)
+        graz = S.grazing(gpos[xi], gtri[xi], vpos[ki], vtri[ki], eps=prm["t_eps"], delta_rel=BAND)
+        # reported, not asserted: how many would still be excused by a band ten times narrower
+        finer = int(S.grazing(gpos[xi], gtri[xi], vpos[ki], vtri[ki], eps=prm["t_eps"], delta_rel=BAND / 10).sum())
+        print(f"{label}: {int(graz.sum())} of {len(xi)} disagreements grazing at {BAND:g} of the diagonal, "
+              f"{finer} at {BAND / 10:g}", flush=True)
         for j in np.nonzero(graz == 0)[0][:20]:
             print(f"{label}: non-grazing pair px={pixels[xi[j]]} tri_p={gtri[xi[j]]} x={gpos[xi[j]].tolist()} "
                   f"vpl={ki[j]} tri_k={vtri[ki[j]]} y={vpos[ki[j]].tolist()} "

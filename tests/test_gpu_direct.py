@@ -14,6 +14,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as orc  # noqa: E402
 from paper_2203_11484_amd import scenes  # noqa: E402
 from tests import helpers as H  # noqa: E402
+from tests import oracle_check as OC  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -82,7 +83,9 @@ def _check_direct(vplg, ctx, sc, label, eps=1e-4):
     if len(dis[0]):
         xi, ki = dis
         graz = S.grazing(gbo["pos"][xi], gbo["tri"][xi], ys[ki], np.full(len(ki), -1, np.int32), eps=eps,
-                         delta_rel=1e-5)
+                         delta_rel=OC.BAND)
+        print(f"{label}: {int(graz.sum())} of {len(xi)} disagreements grazing at {OC.BAND:g} of the diagonal",
+              flush=True)
         assert graz.all(), f"{label}: {(graz == 0).sum()} non-grazing visibility disagreements"
     assert n_dis_cast <= 1e-4 * n_pairs + 0.5
     ov = (dis[0].astype(np.int32), dis[1].astype(np.int32), vis_gpu[dis]) if len(dis[0]) else None

@@ -3,7 +3,7 @@
 Gather: the oracle's G-buffer and VPL set (rounded to float32) feed both
 sides, or (the device path) the G-buffer and VPL set the GPU made are
 downloaded and fed to the oracle.  Every visibility disagreement must be
-grazing (moving an endpoint by 1e-5 of the scene diagonal flips the oracle's
+grazing (moving an endpoint by 1e-7 of the scene diagonal flips the oracle's
 answer) and at most 1e-4 of the pairs; radiance must then match per channel
 within 1e-4 relative, with the oracle re-evaluated on the GPU's bit for the
 disagreeing pairs (tests/oracle_check.py).
@@ -183,15 +183,29 @@ def test_gbuffer_parity(vplg, ctx, name, size):
     vplg.scene_release(ctx, sid)
 
 
-DEVICE_CASES = [("cornell", None, 0), ("room20k", 384, 11), ("room200k", 96, 13)]
+DEVICE_CASES = [("cornell", None, 0, 0), ("room20k", 384, 11, 32), ("room200k", 96, 13, 32)]
 
 
-@pytest.mark.parametrize("name,n_px,seed", DEVICE_CASES, ids=[c[0] for c in DEVICE_CASES])
-def test_device_path_matches_oracle(vplg, ctx, name, n_px, seed):
+def _tail_pixels(W, H, n_tail, seed):
+    """One pixel in each of n_tail seeded 8 x 8 tiles among the view's last 2,048 tiles in row-major order:
+    the persistent gather claims them last, and on a full device the tiles it splits into round-group items
+    (two per resident workgroup) are among them."""
+    tx, ty = (W + 7) // 8, (H + 7) // 8
+    rng = np.random.default_rng(seed)
+    tiles = rng.choice(np.arange(max(0, tx * ty - 2048), tx * ty), n_tail, replace=False)
+    px = (tiles % tx) * 8 + rng.integers(0, 8, n_tail)
+    py = (tiles // tx) * 8 + rng.integers(0, 8, n_tail)
+    ok = (px < W) & (py < H)
+    return (py * W + px)[ok]
+
+
+@pytest.mark.parametrize("name,n_px,seed,n_tail", DEVICE_CASES, ids=[c[0] for c in DEVICE_CASES])
+def test_device_path_matches_oracle(vplg, ctx, name, n_px, seed, n_tail):
     """The whole path on the device at the workload's full size, as the bench runs it: G-buffer render,
     VPL generation, gather.  The oracle then evaluates eq. (1) on the G-buffer and VPL set the GPU made
     (downloaded), under the visibility protocol: every pixel of the Cornell box, seeded samples of the
-    rooms.  (The G-buffer and the generation are each held to the oracle by their own tests.)"""
+    rooms, plus pixels of the last tiles (those the gather splits into round-group items).  (The G-buffer
+    and the generation are each held to the oracle by their own tests.)"""
     sc = scenes.make_scene(name)
     cam, prm = sc["camera"], sc["params"]
     S = orc.Scene.from_dict(sc)
@@ -201,7 +215,10 @@ def test_device_path_matches_oracle(vplg, ctx, name, n_px, seed):
     vid = vplg.vpls_generate(ctx, sid, cam, prm)
     L_gpu = _gather_gpu(vplg, ctx, sid, vid, gb, prm)
     P = cam["width"] * cam["height"]
-    pixels = np.arange(P) if n_px is None else np.sort(np.random.default_rng(seed).choice(P, n_px, replace=False))
+    pixels = np.arange(P) if n_px is None else np.random.default_rng(seed).choice(P, n_px, replace=False)
+    if n_tail:
+        pixels = np.concatenate([pixels, _tail_pixels(cam["width"], cam["height"], n_tail, seed + 1)])
+    pixels = np.unique(pixels)
     nd, n = OC.check_gather(vplg, ctx, S, sid, vid, gb, L_gpu, pixels, prm, f"device path {name}")
     print(f"device path {name}: {nd} grazing disagreements of {n} cast pairs")
     vplg.vplset_release(ctx, vid)

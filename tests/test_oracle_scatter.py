@@ -18,6 +18,7 @@ import math
 from fractions import Fraction
 
 import numpy as np
+import pytest
 
 from oracle import oracle as orc
 from paper_2203_11484_amd import scenes
@@ -179,31 +180,33 @@ def test_quad_light_emits_cosine_weighted():
 # the grazing rule
 
 
-def _square_occluder(s=1.0, z=0.5):
-    A, B, C, D = (-s, -s, z), (s, -s, z), (s, s, z), (-s, s, z)
+def _square_occluder(s=1.0, z=0.5, x0=0.0):
+    A, B, C, D = (x0 - s, -s, z), (x0 + s, -s, z), (x0 + s, s, z), (x0 - s, s, z)
     return np.array([[A, B, C], [A, C, D]], np.float32)
 
 
-def test_grazing_flags_only_pairs_within_the_band():
-    tri = _square_occluder()
+@pytest.mark.parametrize("delta_rel", [1e-5, 1e-7])
+def test_grazing_flags_only_pairs_within_the_band(delta_rel):
+    """At the GPU parity protocol's band (1e-7 of the diagonal) and a wider one.  The square spans x in
+    [-2, 0], so the points near its edge x = 0 are exact in float32 even 0.2 band widths from it."""
+    tri = _square_occluder(x0=-1.0)
     S = orc.Scene(tri, np.full((2, 3), 0.5, np.float32), np.zeros(2, np.uint8), use_bvh=False)
-    delta_rel = 1e-5
     delta = delta_rel * S.diag
     # vertical segments z: 0 -> 1 crossing the occluder's plane at s = 1/2, where moving one endpoint
     # by delta along x moves the crossing by delta / 2
-    xs = [(0.0, 0.0, 0, 0),                      # interior: blocked, robust
-          (1.5, 0.0, 1, 0),                      # far outside: visible, robust
-          (1.0 + 0.2 * delta, 0.3, 1, 1),        # just outside the edge x = 1: flips
-          (1.0 - 0.2 * delta, 0.3, 0, 1),        # just inside: flips
-          (1.0 + 3.0 * delta, 0.3, 1, 0),        # outside the band
-          (1.0 - 3.0 * delta, 0.3, 0, 0),        # inside, beyond the band
-          (0.25, 0.25 + 0.1 * delta, 0, 0),      # next to the shared diagonal: blocked either way
-          (0.25, 0.25, 0, 0)]                    # on the shared diagonal (watertight)
+    xs = [(-1.0, 0.0, 0, 0),                     # interior: blocked, robust
+          (0.5, 0.0, 1, 0),                      # far outside: visible, robust
+          (0.2 * delta, 0.3, 1, 1),              # just outside the edge x = 0: flips
+          (-0.2 * delta, 0.3, 0, 1),             # just inside: flips
+          (3.0 * delta, 0.3, 1, 0),              # outside the band
+          (-3.0 * delta, 0.3, 0, 0),             # inside, beyond the band
+          (-0.75, 0.25 + 0.1 * delta, 0, 0),     # next to the shared diagonal: blocked either way
+          (-0.75, 0.25, 0, 0)]                   # on the shared diagonal (watertight)
     x = np.array([[px, py, 0.0] for px, py, _, _ in xs], np.float32)
     y = np.array([[px, py, 1.0] for px, py, _, _ in xs], np.float32)
     # segments z: -8.5 -> 1 crossing at s = 0.947, where moving the far endpoint moves the crossing by
     # 0.947 delta and moving the near one by 0.053 delta: only the far endpoint can flip them
-    ys = [(1.0 + 0.3 * delta, -0.2, 1, 1), (1.0 - 0.3 * delta, -0.2, 0, 1)]
+    ys = [(0.3 * delta, -0.2, 1, 1), (-0.3 * delta, -0.2, 0, 1)]
     xs += ys
     x = np.concatenate([x, np.array([[px, py, -8.5] for px, py, _, _ in ys], np.float32)])
     y = np.concatenate([y, np.array([[px, py, 1.0] for px, py, _, _ in ys], np.float32)])
@@ -214,15 +217,16 @@ def test_grazing_flags_only_pairs_within_the_band():
     assert graz.tolist() == [g for _, _, _, g in xs]
 
 
-def test_grazing_flags_crossings_at_the_segment_ends():
+@pytest.mark.parametrize("delta_rel", [1e-5, 1e-7])
+def test_grazing_flags_crossings_at_the_segment_ends(delta_rel):
     """A crossing just inside the shadow segment's end range s > t_eps flips under the perturbation; one
     in the middle does not."""
-    tri = _square_occluder(z=0.5)
+    tri = _square_occluder(z=0.0)  # in the plane z = 0: the near endpoints z = -a are exact in float32
     S = orc.Scene(tri, np.full((2, 3), 0.5, np.float32), np.zeros(2, np.uint8), use_bvh=False)
-    eps, delta_rel = 1e-4, 1e-5
+    eps = 1e-4
     delta = delta_rel * S.diag
     cases = [(eps + 0.3 * delta, 0, 1), (eps - 0.3 * delta, 1, 1), (0.5, 0, 0), (eps + 3 * delta, 0, 0)]
-    x = np.array([[0.1, 0.2, 0.5 - a] for a, _, _ in cases], np.float32)
+    x = np.array([[0.1, 0.2, -a] for a, _, _ in cases], np.float32)
     y = x + np.array([0, 0, 1.0], np.float32)
     none = np.full(len(cases), -1, np.int32)
     assert S.visibility(x, none, y, none, eps=eps).tolist() == [v for _, v, _ in cases]
