@@ -158,13 +158,13 @@ GBUFFER_CASES = [("cornell", (128, 128)), ("cornell", (100, 75)), ("room20k", (5
 @pytest.mark.parametrize("name,size", GBUFFER_CASES, ids=[f"{n}-{w}x{h}" for n, (w, h) in GBUFFER_CASES])
 def test_gbuffer_parity(vplg, ctx, name, size):
     """The G-buffer at the workloads' full sizes (and two ragged ones), every pixel: the same triangle as
-    the oracle's closest hit except where the oracle flags the pixel's ray as passing within 1e-5 of an
-    edge or of a nearer hit (there either triangle is a correct answer); on every pixel with the same
+    the oracle's closest hit except where the oracle flags the pixel's ray as passing within 1e-7 of its
+    length of an edge or of a nearer hit (there either triangle is a correct answer); on every pixel with the same
     triangle, position within 1e-5 of the scene diagonal, the face normal within 1e-6 and the albedo exact."""
     sc = scenes.make_scene(name, width=size[0], height=size[1])
     S = orc.Scene.from_dict(sc)
     ref = S.gbuffer(sc["camera"])
-    edge = S.gbuffer_edges(sc["camera"], delta=1e-5).astype(bool)
+    edge = S.gbuffer_edges(sc["camera"], delta=1e-7).astype(bool)
     sid = vplg.scene_upload(ctx, sc["tri"], sc["albedo"], sc["flags"], sc["light"])
     gb = vplg.GBuffer(*size)
     vplg.gbuffer_render(ctx, sid, sc["camera"], gb)
