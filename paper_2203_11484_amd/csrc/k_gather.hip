@@ -5,6 +5,11 @@
 // tested against the BVH with both host triangles excluded; occlusion is
 // two-sided and emitters occlude.
 //
+// Each segment's range is first clipped at both ends by the free radii of its
+// end points (the distance within which nothing but the point's own surface
+// plane lies; see free_radius): the parts of the segment next to its end
+// surfaces, where a walk spends many of its node steps, need no test.
+//
 // Shadow rays are traced as wave64 packets: a wave owns an 8 x 8 pixel tile
 // and all 64 rays run to the same VPL, so they are coherent.  The wave walks
 // the BVH together with uniform control flow: node and triangle records are
@@ -34,6 +39,16 @@ constexpr int kChunk = 16;              // VPLs per first-level partial sum of a
 constexpr int kGroups = 4;              // round groups of a tile (the split granularity of the tail)
 constexpr int kSplitRounds = 2;         // split blocks per workgroup of the launch
 constexpr float kInvPi = 0.318309886183790671538f;
+// Free radius of a surface point (see free_radius): triangles whose vertices
+// all lie within kFreeCoplanar x the scene diagonal of the point's plane count
+// as lying in it, and the radius is shortened by kFreeMargin x the largest
+// coordinate magnitude (plus 2^-12 of itself) against its FP32 rounding.
+constexpr float kFreeCoplanar = 4e-8f;
+constexpr float kFreeMargin = 2e-6f;
+// The radius is sought no farther than kFreeCap x the scene diagonal (the
+// walk prunes every box beyond it): the clipping gains little more from
+// larger radii, and a short walk is cheap.
+constexpr float kFreeCap = 0.05f;
 
 // Work memory of the allocation-free gather: the tile counter in the first
 // 256 bytes, then the round-group sums of at most kScratchSplitTiles split
@@ -424,18 +439,198 @@ __device__ __forceinline__ bool traverse(const float4* __restrict__ nodes, const
     return lane_bit(alive, lane);
 }
 
+// Squared distance from p to a box (0 inside it).
+__device__ __forceinline__ float box_dist2(float px, float py, float pz, float lx, float hx, float ly, float hy, float lz,
+                                           float hz)
+{
+    const float ex = fmaxf(fmaxf(lx - px, px - hx), 0.f);
+    const float ey = fmaxf(fmaxf(ly - py, py - hy), 0.f);
+    const float ez = fmaxf(fmaxf(lz - pz, pz - hz), 0.f);
+    return fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+}
+
+// Squared distance from p to the segment a + t e, t in [0, 1], with w = p - a.
+__device__ __forceinline__ float seg_dist2(float wx, float wy, float wz, float ex, float ey, float ez)
+{
+    const float ee = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+    const float we = fmaf(wz, ez, fmaf(wy, ey, wx * ex));
+    const float t = ee > 0.f ? fminf(fmaxf(we / ee, 0.f), 1.f) : 0.f;
+    const float vx = fmaf(-t, ex, wx), vy = fmaf(-t, ey, wy), vz = fmaf(-t, ez, wz);
+    return fmaf(vz, vz, fmaf(vy, vy, vx * vx));
+}
+
+// Squared distance from p to triangle ABC: to its plane where p projects
+// inside it, else to the nearest edge.  Near an edge the two agree, so an
+// inside test that FP32 rounding gets wrong there costs next to nothing.
+__device__ __forceinline__ float tri_dist2(float px, float py, float pz, const Rec& rec)
+{
+    const float ax = rec.q0.x, ay = rec.q0.y, az = rec.q0.z;
+    const float e0x = rec.q1.x - ax, e0y = rec.q1.y - ay, e0z = rec.q1.z - az;  // B - A
+    const float e1x = rec.q2.x - ax, e1y = rec.q2.y - ay, e1z = rec.q2.z - az;  // C - A
+    const float e2x = rec.q2.x - rec.q1.x, e2y = rec.q2.y - rec.q1.y, e2z = rec.q2.z - rec.q1.z;  // C - B
+    const float w0x = px - ax, w0y = py - ay, w0z = pz - az;
+    const float w1x = px - rec.q1.x, w1y = py - rec.q1.y, w1z = pz - rec.q1.z;
+    const float w2x = px - rec.q2.x, w2y = py - rec.q2.y, w2z = pz - rec.q2.z;
+    const float nx = e0y * e1z - e0z * e1y, ny = e0z * e1x - e0x * e1z, nz = e0x * e1y - e0y * e1x;
+    const float nn = fmaf(nz, nz, fmaf(ny, ny, nx * nx));
+    // p's projection is inside iff it is on the inner side of all three edges
+    auto side = [&](float ex, float ey, float ez, float wx, float wy, float wz) {
+        const float cx = ey * wz - ez * wy, cy = ez * wx - ex * wz, cz = ex * wy - ey * wx;
+        return fmaf(nz, cz, fmaf(ny, cy, nx * cx));
+    };
+    const bool inside = nn > 0.f && side(e0x, e0y, e0z, w0x, w0y, w0z) >= 0.f &&
+                        side(e2x, e2y, e2z, w1x, w1y, w1z) >= 0.f && side(-e1x, -e1y, -e1z, w2x, w2y, w2z) >= 0.f;
+    const float h = fmaf(nz, w0z, fmaf(ny, w0y, nx * w0x));
+    const float dp = inside ? h * h / nn : __builtin_inff();
+    const float de = fminf(fminf(seg_dist2(w0x, w0y, w0z, e0x, e0y, e0z), seg_dist2(w1x, w1y, w1z, e2x, e2y, e2z)),
+                           seg_dist2(w0x, w0y, w0z, e1x, e1y, e1z));
+    return fminf(dp, de);
+}
+
+// Whether triangle `rec`'s bounding box is nearer to p than best2 (squared):
+// only then can the triangle lower p's nearest distance.
+__device__ __forceinline__ bool free_tri_near(float px, float py, float pz, const Rec& rec, float best2)
+{
+    const float lx = fminf(fminf(rec.q0.x, rec.q1.x), rec.q2.x), hx = fmaxf(fmaxf(rec.q0.x, rec.q1.x), rec.q2.x);
+    const float ly = fminf(fminf(rec.q0.y, rec.q1.y), rec.q2.y), hy = fmaxf(fmaxf(rec.q0.y, rec.q1.y), rec.q2.y);
+    const float lz = fminf(fminf(rec.q0.z, rec.q1.z), rec.q2.z), hz = fmaxf(fmaxf(rec.q0.z, rec.q1.z), rec.q2.z);
+    return box_dist2(px, py, pz, lx, hx, ly, hy, lz, hz) <= best2;
+}
+
+// Whether a box lies within `tol` of the plane through p with unit normal n
+// (its farthest corner from the plane is no farther): every triangle in it
+// then lies in p's plane and cannot lower p's free radius.
+__device__ __forceinline__ bool box_in_plane(float px, float py, float pz, float nx, float ny, float nz, float lx,
+                                             float hx, float ly, float hy, float lz, float hz, float tol)
+{
+    const float c = fmaf(nz, 0.5f * (lz + hz) - pz, fmaf(ny, 0.5f * (ly + hy) - py, nx * (0.5f * (lx + hx) - px)));
+    const float e = fmaf(fabsf(nz), 0.5f * (hz - lz), fmaf(fabsf(ny), 0.5f * (hy - ly), fabsf(nx) * (0.5f * (hx - lx))));
+    return fabsf(c) + e <= tol;
+}
+
+// Coplanarity tolerance, safety margin and squared cap of the free radius in
+// a scene.
+__device__ __forceinline__ void free_bounds(const DevScene& sc, float* tol, float* margin, float* cap2)
+{
+    const float dx = sc.hi[0] - sc.lo[0], dy = sc.hi[1] - sc.lo[1], dz = sc.hi[2] - sc.lo[2];
+    const float diag = sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    *tol = kFreeCoplanar * diag;
+    *cap2 = (kFreeCap * diag) * (kFreeCap * diag);
+    const float big = fmaxf(fmaxf(fmaxf(fabsf(sc.lo[0]), fabsf(sc.hi[0])), fmaxf(fabsf(sc.lo[1]), fabsf(sc.hi[1]))),
+                            fmaxf(fabsf(sc.lo[2]), fabsf(sc.hi[2])));
+    *margin = kFreeMargin * big;
+}
+
+// The free radius from the squared nearest distance: shortened by 2^-12 of
+// itself and by the margin, never below 0.
+__device__ __forceinline__ float free_safe(float best2, float margin)
+{
+    const float r = sqrtf(best2);
+    return fmaxf(0.f, fmaf(r, -1.0f / 4096.0f, r) - margin);
+}
+
+// Free radius of the surface points of a wave's lanes: a lower bound on the
+// distance from p to every triangle but p's own (ex) and those lying in p's
+// surface plane (unit normal n; all three vertices within `tol` of the plane).
+// A shadow segment leaving p can meet none of those other triangles nearer to
+// p than this, and meets p's own and the coplanar ones only at s = 0 (or, at
+// FP32 rounding of their planes, at a grazing angle), so the part of its range
+// nearer to p needs no test.  The 64 lanes walk the BVH together with uniform
+// control: a child is entered while, for some lane, its box is nearer than
+// that lane's nearest triangle so far and does not lie in the lane's plane
+// (boxes of a floor or a wall are passed over whole); each lane keeps its own
+// minimum.  A lane also tests the triangles of children entered for other
+// lanes, and the in-plane test of a box and of its triangles round
+// differently, so a value may depend on the wave's other points: a pixel's
+// radius is always the one its 8 x 8 tile's wave computes (gather_tile, and
+// the dump, which walks the same tiles).  The search stops at the cap (a lane
+// with no triangle to consider within it gets the cap, shortened like any
+// radius); inactive lanes get 0.
+__device__ float free_radius(const DevScene& sc, float px, float py, float pz, float nx, float ny, float nz, int ex,
+                             bool act, int lane)
+{
+    float tol, margin, cap2;
+    free_bounds(sc, &tol, &margin, &cap2);
+    const float4* __restrict__ nodes = sc.nodes;
+    const float4* __restrict__ tris = sc.tris;  // identity plane: vertices in (x, y, z) order
+    // boxes are padded outward, so a box's distance is below that of any
+    // triangle in it by more than FP32 rounding: pruning at best2 is exact
+    float best2 = act ? cap2 : -1.f;
+    int slot = 0;
+    int sp = 0;
+    int node = 0;
+    const int lead = __builtin_ctzll(ballot(act) | (1ull << 63));
+    while (true) {
+        const Rec nd = load_rec(nodes, node);
+        const int c0 = __float_as_int(nd.q3.x), c1 = __float_as_int(nd.q3.y), kk = __float_as_int(nd.q3.z);
+        const float d0 = box_dist2(px, py, pz, nd.q0.x, nd.q0.y, nd.q0.z, nd.q0.w, nd.q2.x, nd.q2.y);
+        const float d1 = box_dist2(px, py, pz, nd.q1.x, nd.q1.y, nd.q1.z, nd.q1.w, nd.q2.z, nd.q2.w);
+        bool e0 = ballot(d0 < best2 && !box_in_plane(px, py, pz, nx, ny, nz, nd.q0.x, nd.q0.y, nd.q0.z, nd.q0.w, nd.q2.x,
+                                                     nd.q2.y, tol)) != 0;
+        bool e1 = ballot(d1 < best2 && !box_in_plane(px, py, pz, nx, ny, nz, nd.q1.x, nd.q1.y, nd.q1.z, nd.q1.w, nd.q2.z,
+                                                     nd.q2.w, tol)) != 0;
+        for (int k = 0; k < 2; ++k) {
+            const int cnt = k == 0 ? (kk & 0xffff) : (kk >> 16);
+            const bool enter = k == 0 ? e0 : e1;
+            if (cnt == 0 || !enter) continue;
+            const int first = k == 0 ? c0 : c1;
+            for (int i = first; i < first + cnt; ++i) {
+                const Rec rec = load_rec(tris, i);
+                const bool near = free_tri_near(px, py, pz, rec, best2);
+                if (ballot(near) == 0) continue;  // the triangle's box is no nearer than any lane's best
+                const float oa = fmaf(nz, rec.q0.z - pz, fmaf(ny, rec.q0.y - py, nx * (rec.q0.x - px)));
+                const float ob = fmaf(nz, rec.q1.z - pz, fmaf(ny, rec.q1.y - py, nx * (rec.q1.x - px)));
+                const float oc = fmaf(nz, rec.q2.z - pz, fmaf(ny, rec.q2.y - py, nx * (rec.q2.x - px)));
+                const bool skip = __float_as_int(rec.q0.w) == ex || fmaxf(fmaxf(fabsf(oa), fabsf(ob)), fabsf(oc)) <= tol;
+                if (near && !skip) best2 = fminf(best2, tri_dist2(px, py, pz, rec));
+            }
+            if (k == 0) e0 = false;
+            else e1 = false;
+        }
+        if (e0 && e1) {
+            // both: the one nearer the lead lane first
+            const bool first1 = __builtin_amdgcn_readlane(__float_as_int(d1), lead) <
+                                __builtin_amdgcn_readlane(__float_as_int(d0), lead);  // non-negative floats: int order
+            slot = lane == sp ? (first1 ? c0 : c1) : slot;
+            ++sp;
+            node = first1 ? c1 : c0;
+        } else if (e0) {
+            node = c0;
+        } else if (e1) {
+            node = c1;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = __builtin_amdgcn_readlane(slot, sp);
+        }
+    }
+    return act ? free_safe(best2, margin) : 0.f;
+}
+
 // Any-hit test of a wave's 64 segments o + s d, s in (tlo, thi), walked as
 // one packet.  `act` marks the lanes with a ray; ex0 (per lane) and ex1
-// (wave-uniform) are the excluded host triangles.  Returns, per lane,
-// whether its ray is active and unblocked.  All control is wave-uniform:
-// `alive` is the mask of unblocked lanes, and the traversal stack holds
-// entry i in lane i of `slot`.
+// (wave-uniform) are the excluded host triangles; rx (per lane) and ry
+// (wave-uniform) are the free radii of the segments' ends (0: none), which
+// clip each range to s in (max(tlo, rx / |d|), min(thi, 1 - ry / |d|)): no
+// triangle the test considers lies nearer an end than its radius.  A segment
+// whose clipped range is empty is unblocked without a walk.  Returns, per
+// lane, whether its ray is active and unblocked.  All control is
+// wave-uniform: `alive` is the mask of unblocked lanes, and the traversal
+// stack holds entry i in lane i of `slot`.
 template <bool COUNT>
 __device__ __forceinline__ bool packet_visible(const DevScene& sc, float ox, float oy, float oz, float dx, float dy, float dz,
-                               bool act, float tlo, float thi, int ex0, int ex1, int lane, Counters& cnt)
+                               bool act, float tlo, float thi, int ex0, int ex1, float rx, float ry, int lane,
+                               Counters& cnt)
 {
-    // slab distances in units of the segment's range: u = (s - tlo) * us
-    const float us = 1.0f / (thi - tlo);
+    const float il = __builtin_amdgcn_rsqf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    tlo = fmaxf(tlo, rx * il);
+    thi = fminf(thi, fmaf(-ry, il, 1.0f));
+    const bool open = act && !(tlo < thi);  // the whole range lies within the free radii
+    act = act && tlo < thi;
+    if (ballot(act) == 0) return open;
+    // slab distances in units of the segment's range: u = (s - tlo) * us (an
+    // approximate reciprocal only scales every distance alike)
+    const float us = rcpf(thi - tlo);
     const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
     SlabRay r;
     r.ix = ix * us;
@@ -471,17 +666,19 @@ __device__ __forceinline__ bool packet_visible(const DevScene& sc, float ox, flo
         __float_as_int(fmaf(0.5f, dy, oy)), lead))));
     const int mkz = __builtin_amdgcn_readfirstlane(order_key(__int_as_float(__builtin_amdgcn_readlane(
         __float_as_int(fmaf(0.5f, dz, oz)), lead))));
+    bool vis;
     switch (oct) {
-    case 0: return traverse<COUNT, 0>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
-    case 1: return traverse<COUNT, 1>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
-    case 2: return traverse<COUNT, 2>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
-    case 3: return traverse<COUNT, 3>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
-    case 4: return traverse<COUNT, 4>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
-    case 5: return traverse<COUNT, 5>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
-    case 6: return traverse<COUNT, 6>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
-    case 7: return traverse<COUNT, 7>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
-    default: return traverse<COUNT, 8>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt);
+    case 0: vis = traverse<COUNT, 0>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt); break;
+    case 1: vis = traverse<COUNT, 1>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt); break;
+    case 2: vis = traverse<COUNT, 2>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt); break;
+    case 3: vis = traverse<COUNT, 3>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt); break;
+    case 4: vis = traverse<COUNT, 4>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt); break;
+    case 5: vis = traverse<COUNT, 5>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt); break;
+    case 6: vis = traverse<COUNT, 6>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt); break;
+    case 7: vis = traverse<COUNT, 7>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt); break;
+    default: vis = traverse<COUNT, 8>(nodes, tris, r, wr, act, tlo, thi, ex0, ex1, mkx, mky, mkz, lane, cnt); break;
     }
+    return vis || open;
 }
 
 // Pixel of lane `tid` in a 16 x 16 tile: each wave64 owns an 8 x 8 quadrant.
@@ -523,6 +720,12 @@ __device__ __forceinline__ float3 gather_tile(const GatherArgs& a, int tile, int
         nx = a.gb.nrm[0][p]; ny = a.gb.nrm[1][p]; nz = a.gb.nrm[2][p];
     }
     const bool active = valid && tp >= 0;
+    // free radii of the tile's receivers: wave 0 of the group walks for them, the group reads them from
+    // LDS (the slot is free until the group's first round-group sums)
+    if (wave == 0) red[0][0][lane] = free_radius(a.scene, x, y, z, nx, ny, nz, tp, active, lane);
+    sync();
+    const float rx = red[0][0][lane];
+    sync();
     const int M = *a.vpls.count;
     const float C = a.g_clamp;
     const float tlo = a.t_eps, thi = 1.0f - a.t_eps;
@@ -556,7 +759,7 @@ __device__ __forceinline__ float3 gather_tile(const GatherArgs& a, int tile, int
                 float r2 = dx * dx + dy * dy + dz * dz;
                 float gt = fminf(C, cp * ck * rcpf(r2 * r2));
                 bool vis = packet_visible<COUNT>(a.scene, x, y, z, dx, dy, dz, act, tlo, thi, tp, __float_as_int(v0.w),
-                                                 lane, cnt);
+                                                 rx, a.vpl_free ? v1.w : 0.f, lane, cnt);
                 if (COUNT) {
                     const unsigned long long am = ballot(act), vm = ballot(vis);
                     if (act && !vis) cnt.blocked++;
@@ -657,6 +860,16 @@ struct BlockSync {
     __device__ void operator()() const { __syncthreads(); }
 };
 
+// The workgroup barriers of one gather_tile call (two around the free radii,
+// two around the group sums), for the waves of a group that has no tile.
+__device__ __forceinline__ void tile_skip_barriers()
+{
+    __syncthreads();
+    __syncthreads();
+    __syncthreads();
+    __syncthreads();
+}
+
 // Persistent gather of one view: each workgroup (G tile groups of w waves,
 // one VPL slice each) claims work items from a device counter until none is
 // left, so the tiles' uneven costs spread over all CUs of all XCDs (a fixed
@@ -699,9 +912,8 @@ __device__ __forceinline__ void gather_persistent(const GatherArgs& a, unsigned 
         const int blk = whole ? item : full + si / kGroups;
         const int tile = block_tile(blk, grp, G, W, H);
         float (*red)[3][64] = s_red + grp * kGroups * nw;
-        if (tile < 0) {  // every wave takes part in both barriers
-            __syncthreads();
-            __syncthreads();
+        if (tile < 0) {  // every wave takes part in the tile's barriers
+            tile_skip_barriers();
             continue;
         }
         const float3 S = gather_tile<COUNT>(a, tile, whole ? 0 : g, whole ? kGroups : g + 1, wg, nw, lane, red, cnt,
@@ -784,7 +996,7 @@ __global__ __launch_bounds__(64 * BW) __attribute__((amdgpu_waves_per_eu(8))) vo
         const int group = wave / w;
         const int G = a.px_tiles;
         const int blk = (item - tab->prefix[lo]) * (groups / G) + group / G;
-        // every wave takes part in both barriers, including groups past the last block
+        // every wave takes part in the tile's barriers, including groups past the last block
         const int t = blk < view_blocks(a.gb.width, a.gb.height, G) ? block_tile(blk, group % G, G, a.gb.width,
                                                                                   a.gb.height)
                                                                       : -1;
@@ -793,8 +1005,7 @@ __global__ __launch_bounds__(64 * BW) __attribute__((amdgpu_waves_per_eu(8))) vo
                                                 pairs, BlockSync());
             if (wave % w == 0) tile_out(a, t, lane, S);
         } else {
-            __syncthreads();
-            __syncthreads();
+            tile_skip_barriers();
         }
     }
 }
@@ -814,8 +1025,36 @@ __global__ __launch_bounds__(BLOCK) void k_vis_dump(VisDumpArgs a)
     if (p >= a.gb.width * a.gb.height) p = -1;  // the pixel list lives on the device: checked here
     const int tp = p >= 0 ? a.gb.tri[p] : -1;
     const bool ok = p >= 0 && tp >= 0;
-    float x = 0, y = 0, z = 0;
-    if (ok) { x = a.gb.pos[0][p]; y = a.gb.pos[1][p]; z = a.gb.pos[2][p]; }
+    float x = 0, y = 0, z = 0, nx = 0, ny = 0, nz = 0;
+    if (ok) {
+        x = a.gb.pos[0][p]; y = a.gb.pos[1][p]; z = a.gb.pos[2][p];
+        nx = a.gb.nrm[0][p]; ny = a.gb.nrm[1][p]; nz = a.gb.nrm[2][p];
+    }
+    // the gather's clipping with its free radii: a pixel's radius is the one its 8 x 8 tile's wave
+    // computes, so the dump walks each tile its pixels fall in with that tile's 64 pixels, lane for lane
+    const int W = a.gb.width, H = a.gb.height, tiles_x = (W + 7) >> 3;
+    const int my_tile = p >= 0 ? (p / W >> 3) * tiles_x + ((p % W) >> 3) : -1;
+    const int my_pos = p >= 0 ? ((p % W) & 7) | ((p / W & 7) << 3) : 0;
+    float rx = 0.f;
+    unsigned long long todo = ballot(ok);
+    while (todo) {
+        const int T = __builtin_amdgcn_readlane(my_tile, __builtin_ctzll(todo));
+        const int qx = (T % tiles_x) * 8 + (lane & 7), qy = (T / tiles_x) * 8 + (lane >> 3);
+        const bool qv = qx < W && qy < H;
+        const int q = qy * W + qx;
+        int qt = -1;
+        float qpx = 0, qpy = 0, qpz = 0, qnx = 0, qny = 0, qnz = 0;
+        if (qv) {
+            qt = a.gb.tri[q];
+            qpx = a.gb.pos[0][q]; qpy = a.gb.pos[1][q]; qpz = a.gb.pos[2][q];
+            qnx = a.gb.nrm[0][q]; qny = a.gb.nrm[1][q]; qnz = a.gb.nrm[2][q];
+        }
+        const float r = free_radius(a.scene, qpx, qpy, qpz, qnx, qny, qnz, qt, qv && qt >= 0, lane);
+        const float mine = __shfl(r, my_pos, 64);
+        const bool here = ok && my_tile == T;
+        if (here) rx = mine;
+        todo &= ~ballot(here);
+    }
     const int M = *a.vpls.count;
     const float4* __restrict__ vp = a.vpls.pack;
     Counters cnt;
@@ -825,10 +1064,11 @@ __global__ __launch_bounds__(BLOCK) void k_vis_dump(VisDumpArgs a)
             int k = w * 32 + b;
             if (k >= M) break;
             const float4 v0 = load_c4(vp, 3 * k);
+            const float ry = a.vpl_free ? load_c4(vp, 3 * k + 1).w : 0.f;
             bool vis = false;
             if (ballot(ok) != 0)
                 vis = packet_visible<false>(a.scene, x, y, z, v0.x - x, v0.y - y, v0.z - z, ok, a.t_eps,
-                                            1.0f - a.t_eps, tp, __float_as_int(v0.w), lane, cnt);
+                                            1.0f - a.t_eps, tp, __float_as_int(v0.w), rx, ry, lane, cnt);
             if (vis) bits |= 1u << b;
         }
         if (in) a.bits[(size_t)gid * a.words + w] = bits;
@@ -871,7 +1111,7 @@ __global__ __launch_bounds__(BLOCK) void k_direct(DirectArgs a)
         const bool act = valid && cx > 0.f && cl > 0.f;
         if (ballot(act) == 0) continue;
         const float g = quad ? (cx * cl) * rcpf(r2 * r2) : cx * rcpf(r2 * sqrtf(r2));
-        const bool vis = packet_visible<false>(a.scene, x, y, z, wx, wy, wz, act, tlo, thi, tp, -1, lane, cnt);
+        const bool vis = packet_visible<false>(a.scene, x, y, z, wx, wy, wz, act, tlo, thi, tp, -1, 0.f, 0.f, lane, cnt);
         if (vis) G += g;
     }
     G *= quad ? 1.0f / (16.0f * 3.14159265358979323846f) : 1.0f / (4.0f * 3.14159265358979323846f);
@@ -972,21 +1212,47 @@ __global__ __launch_bounds__(BLOCK) void k_gbuffer(GBufferArgs a)
 }
 
 // Interleave the SoA planes of a VPL set into the gather layout.
-__global__ void k_pack_vpls(DevVpls v)
+// The gather's VPL records; with a scene, each VPL's free radius in that
+// scene goes to the .w of its second record (else 0).  Every lane of a wave
+// takes part in the radius walk.
+// The gather's VPL records of a set with no scene (free radius 0), one thread per VPL.
+__global__ __launch_bounds__(BLOCK) void k_pack_vpls_plain(DevVpls v)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= *v.count || i >= v.capacity) return;
     v.pack[3 * i] = make_float4(v.px[i], v.py[i], v.pz[i], __int_as_float(v.tri[i]));
     v.pack[3 * i + 1] = make_float4(v.nx[i], v.ny[i], v.nz[i], 0.f);
     v.pack[3 * i + 2] = make_float4(v.ir[i], v.ig[i], v.ib[i], 0.f);
 }
 
+// The gather's VPL records, one wave per VPL; with a scene, the VPL's free
+// radius in that scene goes to the .w of its second record (else 0).  Lane 0
+// alone drives the radius walk (the other lanes are idle in it), so the value
+// depends on the VPL alone, and with one wave per VPL the short, latency-bound
+// walks run side by side over the whole device.
+__global__ __launch_bounds__(64) void k_pack_vpls(DevScene sc, DevVpls v, int with_radius)
+{
+    const int i = blockIdx.x;
+    if (i >= *v.count || i >= v.capacity) return;  // the whole wave
+    const int lane = threadIdx.x;
+    const float px = v.px[i], py = v.py[i], pz = v.pz[i];
+    const float nx = v.nx[i], ny = v.ny[i], nz = v.nz[i];
+    const int tri = v.tri[i];
+    const float r = with_radius ? free_radius(sc, px, py, pz, nx, ny, nz, tri, lane == 0, lane) : 0.f;
+    if (lane == 0) {
+        v.pack[3 * i] = make_float4(px, py, pz, __int_as_float(tri));
+        v.pack[3 * i + 1] = make_float4(nx, ny, nz, r);
+        v.pack[3 * i + 2] = make_float4(v.ir[i], v.ig[i], v.ib[i], 0.f);
+    }
+}
+
 }  // namespace
 
-hipError_t launch_pack_vpls(const DevVpls& v, hipStream_t s)
+hipError_t launch_pack_vpls(const DevScene* sc, const DevVpls& v, hipStream_t s)
 {
     if (v.capacity == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_vpls, dim3((v.capacity + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, v);
+    if (sc) hipLaunchKernelGGL(k_pack_vpls, dim3(v.capacity), dim3(64), 0, s, *sc, v, 1);
+    else hipLaunchKernelGGL(k_pack_vpls_plain, dim3((v.capacity + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, v);
     return hipGetLastError();
 }
 

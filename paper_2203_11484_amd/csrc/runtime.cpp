@@ -377,6 +377,7 @@ int vplg_scene_upload(vplg_context* ctx, const float* tri_xyz, const float* tri_
     }
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     uint64_t id = ctx->next_id++;
+    so->id = id;
     ctx->scenes[id] = so;
     *scene_id = id;
     return VPLG_OK;
@@ -583,7 +584,8 @@ int launch_genset(SceneObj* so, VplSetObj* v, const vplg_camera* cam, const vplg
     GenParams gp{p->k_near,  p->n_far,     p->max_bounces, p->max_paths,  p->d_near,       p->patch_h,
                  p->t_eps,   p->walk_near, p->jitter,      p->brightness, p->walk_schedule};
     HIPCHK(launch_generate(so->dev, so->light, cb, gp, v->dev, v->gen, s));
-    HIPCHK(launch_pack_vpls(v->dev, s));
+    HIPCHK(launch_pack_vpls(&so->dev, v->dev, s));
+    v->radius_scene = so->id;
     HIPCHK(hipEventRecord(v->done, s));
     return VPLG_OK;
 }
@@ -718,7 +720,7 @@ int vplg_vpls_upload(vplg_context* ctx, const float* pos, const float* nrm, cons
     if (e == hipSuccess && n > 0) e = hipMemcpyAsync(dv.tri, host_tri, (size_t)n * 4, hipMemcpyHostToDevice, s);
     int32_t cnt = n;
     if (e == hipSuccess) e = hipMemcpyAsync(dv.count, &cnt, 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_pack_vpls(dv, s);
+    if (e == hipSuccess) e = launch_pack_vpls(nullptr, dv, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         release_set(ctx, v);
@@ -876,6 +878,7 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
     a->split_cap = 0;
     a->split_full = a->split_count = 0;
     a->split_part = nullptr;
+    a->vpl_free = v->radius_scene != 0 && v->radius_scene == so->id;
     // tile_vpl: waves (VPL slices) per 8 x 8 tile, tile_px: pixels per work item; tile_vpl 0 leaves the shape
     // to the autotuned table (else the tile-count rule), with tile_px, if given, fixing the pixel block
     int G = px_tiles_of(p->tile_px);
@@ -1028,6 +1031,7 @@ int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t v
     a.words = (M + 31) / 32;
     a.bits = vis_bits;
     a.t_eps = p->t_eps;
+    a.vpl_free = v->radius_scene != 0 && v->radius_scene == so->id;
     HIPCHK(launch_vis_dump(a, (hipStream_t)stream));
     return VPLG_OK;
 }

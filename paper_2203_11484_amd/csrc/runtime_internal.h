@@ -41,6 +41,7 @@ struct PatchIndex {
 };
 
 struct SceneObj {
+    uint64_t id = 0;
     DevScene dev;
     DevLight light;
     std::vector<Alloc> allocs;
@@ -63,6 +64,8 @@ struct VplSetObj {
     uint64_t scene_id = 0;
     double patch_h = 0.0;
     hipEvent_t done = nullptr;
+    // the scene whose free radii the VPL records hold (0: none, an uploaded set)
+    uint64_t radius_scene = 0;
 };
 
 // Persistent batched gather: device work table and view descriptors, their

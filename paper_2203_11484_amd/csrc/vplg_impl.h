@@ -77,7 +77,9 @@ struct DevVpls {
     float* ir = nullptr; float* ig = nullptr; float* ib = nullptr;
     int32_t* tri = nullptr;
     int32_t* count = nullptr;  // device int32: number of valid VPLs
-    // gather layout: three float4 per VPL, (pos, tri bits), (nrm, 0), (I, 0)
+    // gather layout: three float4 per VPL, (pos, tri bits), (nrm, free radius), (I, 0); the free radius
+    // (the distance within which no triangle but the VPL's own and those in its plane lies) is that of
+    // the scene the set was generated for, 0 for an uploaded set
     float4* pack = nullptr;
     int capacity = 0;
 };
@@ -111,6 +113,9 @@ struct GatherArgs {
     int split_cap;
     int split_full, split_count;
     float* split_part;
+    // 1 when the VPL records' free radii belong to this scene (the set was generated for it): the
+    // shadow segments are then clipped at both ends, else at the receiver's end only
+    int vpl_free;
 };
 
 // Work table of a batched gather: views sorted by the caller, prefix[v] =
@@ -135,6 +140,7 @@ struct VisDumpArgs {
     int words;  // ceil(capacity / 32)
     uint32_t* bits;
     float t_eps;
+    int vpl_free;  // as in GatherArgs
 };
 
 // Direct term L_e(y) of eq. (1) over a G-buffer.
@@ -243,7 +249,8 @@ hipError_t launch_gather_batch(const BatchTable* tab, const GatherArgs* views, u
 hipError_t gather_batch_occupancy(int block_waves, int* blocks_per_cu);
 hipError_t launch_gbuffer(const GBufferArgs& a, hipStream_t s);
 hipError_t launch_direct(const DirectArgs& a, hipStream_t s);
-hipError_t launch_pack_vpls(const DevVpls& v, hipStream_t s);
+// Pack the gather's VPL records; with a scene (non-null), each VPL's free radius in it.
+hipError_t launch_pack_vpls(const DevScene* sc, const DevVpls& v, hipStream_t s);
 
 hipError_t launch_patch_levels(const DevScene& sc, double h, int32_t* level, long long* counts, hipStream_t s);
 hipError_t launch_scan_i64(const long long* in, long long* out, int n, long long* tmp, int tmp_len,
