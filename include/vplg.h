@@ -186,11 +186,12 @@ typedef struct {
  * decision is taken in FP64.  Device work is enqueued on `stream`; the
  * first generation for a (scene, patch_h) pair synchronises once to size
  * the patch arrays.  The VPL count is known after the stream completes
- * (vplg_vplset_count / vplg_vplset_stats wait for it).  The set also records
- * each VPL's free radius in the scene (the distance within which no triangle
- * but the VPL's own and those in its plane lies), which gathers against that
- * same scene use to shorten the shadow rays' VPL ends; gathers against any
- * other scene, and uploaded sets, do without. */
+ * (vplg_vplset_count / vplg_vplset_stats wait for it).  In a scene of at
+ * least 1,024 triangles the set also records each VPL's free radius (the
+ * distance within which no triangle but the VPL's own and those in its plane
+ * lies), which gathers against that same scene use to shorten the shadow
+ * rays' VPL ends; gathers against any other scene, and uploaded sets, do
+ * without. */
 int vplg_vpls_generate(vplg_context* ctx, uint64_t scene_id, const vplg_camera* cam, const vplg_gen_params* p,
                        void* stream, uint64_t* vplset_id);
 /* Generate again into an existing generated set (same scene, k_near, n_far

@@ -722,7 +722,7 @@ __device__ __forceinline__ float3 gather_tile(const GatherArgs& a, int tile, int
     const bool active = valid && tp >= 0;
     // free radii of the tile's receivers: wave 0 of the group walks for them, the group reads them from
     // LDS (the slot is free until the group's first round-group sums)
-    if (wave == 0) red[0][0][lane] = free_radius(a.scene, x, y, z, nx, ny, nz, tp, active, lane);
+    if (wave == 0) red[0][0][lane] = a.free_ends & 1 ? free_radius(a.scene, x, y, z, nx, ny, nz, tp, active, lane) : 0.f;
     sync();
     const float rx = red[0][0][lane];
     sync();
@@ -759,7 +759,7 @@ __device__ __forceinline__ float3 gather_tile(const GatherArgs& a, int tile, int
                 float r2 = dx * dx + dy * dy + dz * dz;
                 float gt = fminf(C, cp * ck * rcpf(r2 * r2));
                 bool vis = packet_visible<COUNT>(a.scene, x, y, z, dx, dy, dz, act, tlo, thi, tp, __float_as_int(v0.w),
-                                                 rx, a.vpl_free ? v1.w : 0.f, lane, cnt);
+                                                 rx, a.free_ends & 2 ? v1.w : 0.f, lane, cnt);
                 if (COUNT) {
                     const unsigned long long am = ballot(act), vm = ballot(vis);
                     if (act && !vis) cnt.blocked++;
@@ -1036,7 +1036,7 @@ __global__ __launch_bounds__(BLOCK) void k_vis_dump(VisDumpArgs a)
     const int my_tile = p >= 0 ? (p / W >> 3) * tiles_x + ((p % W) >> 3) : -1;
     const int my_pos = p >= 0 ? ((p % W) & 7) | ((p / W & 7) << 3) : 0;
     float rx = 0.f;
-    unsigned long long todo = ballot(ok);
+    unsigned long long todo = a.free_ends & 1 ? ballot(ok) : 0ull;
     while (todo) {
         const int T = __builtin_amdgcn_readlane(my_tile, __builtin_ctzll(todo));
         const int qx = (T % tiles_x) * 8 + (lane & 7), qy = (T / tiles_x) * 8 + (lane >> 3);
@@ -1064,7 +1064,7 @@ __global__ __launch_bounds__(BLOCK) void k_vis_dump(VisDumpArgs a)
             int k = w * 32 + b;
             if (k >= M) break;
             const float4 v0 = load_c4(vp, 3 * k);
-            const float ry = a.vpl_free ? load_c4(vp, 3 * k + 1).w : 0.f;
+            const float ry = a.free_ends & 2 ? load_c4(vp, 3 * k + 1).w : 0.f;
             bool vis = false;
             if (ballot(ok) != 0)
                 vis = packet_visible<false>(a.scene, x, y, z, v0.x - x, v0.y - y, v0.z - z, ok, a.t_eps,

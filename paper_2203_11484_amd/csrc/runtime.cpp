@@ -584,8 +584,9 @@ int launch_genset(SceneObj* so, VplSetObj* v, const vplg_camera* cam, const vplg
     GenParams gp{p->k_near,  p->n_far,     p->max_bounces, p->max_paths,  p->d_near,       p->patch_h,
                  p->t_eps,   p->walk_near, p->jitter,      p->brightness, p->walk_schedule};
     HIPCHK(launch_generate(so->dev, so->light, cb, gp, v->dev, v->gen, s));
-    HIPCHK(launch_pack_vpls(&so->dev, v->dev, s));
-    v->radius_scene = so->id;
+    const bool radii = so->dev.n_tris >= kFreeMinTris;
+    HIPCHK(launch_pack_vpls(radii ? &so->dev : nullptr, v->dev, s));
+    v->radius_scene = radii ? so->id : 0;
     HIPCHK(hipEventRecord(v->done, s));
     return VPLG_OK;
 }
@@ -878,7 +879,7 @@ int gather_args(vplg_context* ctx, SceneObj* so, VplSetObj* v, const vplg_gbuffe
     a->split_cap = 0;
     a->split_full = a->split_count = 0;
     a->split_part = nullptr;
-    a->vpl_free = v->radius_scene != 0 && v->radius_scene == so->id;
+    a->free_ends = so->dev.n_tris < kFreeMinTris ? 0 : 1 | (v->radius_scene == so->id ? 2 : 0);
     // tile_vpl: waves (VPL slices) per 8 x 8 tile, tile_px: pixels per work item; tile_vpl 0 leaves the shape
     // to the autotuned table (else the tile-count rule), with tile_px, if given, fixing the pixel block
     int G = px_tiles_of(p->tile_px);
@@ -1031,7 +1032,7 @@ int vplg_gather_visibility_dump(vplg_context* ctx, uint64_t scene_id, uint64_t v
     a.words = (M + 31) / 32;
     a.bits = vis_bits;
     a.t_eps = p->t_eps;
-    a.vpl_free = v->radius_scene != 0 && v->radius_scene == so->id;
+    a.free_ends = so->dev.n_tris < kFreeMinTris ? 0 : 1 | (v->radius_scene == so->id ? 2 : 0);
     HIPCHK(launch_vis_dump(a, (hipStream_t)stream));
     return VPLG_OK;
 }

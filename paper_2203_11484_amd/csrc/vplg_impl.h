@@ -113,9 +113,9 @@ struct GatherArgs {
     int split_cap;
     int split_full, split_count;
     float* split_part;
-    // 1 when the VPL records' free radii belong to this scene (the set was generated for it): the
-    // shadow segments are then clipped at both ends, else at the receiver's end only
-    int vpl_free;
+    // which ends of the shadow segments are clipped by free radii: bit 0 the receivers' (walked per
+    // tile), bit 1 the VPLs' (their records' radii, when the set was generated for this scene)
+    int free_ends;
 };
 
 // Work table of a batched gather: views sorted by the caller, prefix[v] =
@@ -140,7 +140,7 @@ struct VisDumpArgs {
     int words;  // ceil(capacity / 32)
     uint32_t* bits;
     float t_eps;
-    int vpl_free;  // as in GatherArgs
+    int free_ends;  // as in GatherArgs
 };
 
 // Direct term L_e(y) of eq. (1) over a G-buffer.
@@ -222,6 +222,10 @@ struct GenBuffers {
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
+// Scenes of fewer triangles gather without free radii: their walks are short,
+// and the receivers' radius walks would cost more than the clipping saves.
+constexpr int kFreeMinTris = 1024;
+
 // Persistent single-view gather: resets `counter` (a device word private to
 // stream `s`) and launches `blocks` workgroups that claim tiles from it.
 hipError_t launch_gather(const GatherArgs& a, bool counted, unsigned int* counter, int blocks, hipStream_t s);

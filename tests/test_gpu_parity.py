@@ -333,30 +333,30 @@ def test_gather_equals_instrumented_walk(vplg, ctx, name):
 def test_vpl_radii_belong_to_the_generating_scene(vplg, ctx):
     """A generated set's VPL records carry the VPLs' free radii in the scene they were generated for (the
     gather clips each shadow segment's VPL end by it); gathered against another scene the gather must not
-    use them.  Scene B is the Cornell box with a panel 0.02 above the floor, well inside the free radii the
-    floor VPLs have in the plain box, so with the plain box's radii the segments to floor VPLs would skip
-    the panel.  The set generated in the plain box, gathered in B, must meet the oracle in B under the
+    use them.  Scene B is a procedural room with a panel 0.02 above its floor, well inside the free radii
+    the floor VPLs have in the room without it, so with those radii the segments to floor VPLs would skip
+    the panel.  The set generated in the plain room, gathered in B, must meet the oracle in B under the
     protocol, every pixel."""
     W, Hh = 64, 48
-    scA = scenes.make_scene("cornell", width=W, height=Hh)
+    scA = scenes.procedural_room(7, 6, 6, 2, 2, width=W, height=Hh)
+    assert len(scA["tri"]) >= 1024, "a scene small enough to skip the clipping would test nothing here"
     prm = scA["params"]
     sidA = vplg.scene_upload(ctx, scA["tri"], scA["albedo"], scA["flags"], scA["light"])
     vid = vplg.vpls_generate(ctx, sidA, scA["camera"], prm)
-    y = 0.02
-    panel = np.array([[[0.02, y, 0.02], [0.98, y, 0.02], [0.98, y, 0.98]],
-                      [[0.02, y, 0.02], [0.98, y, 0.98], [0.02, y, 0.98]]], np.float32)
+    y, a, b = 0.02, 0.05, 9.95
+    panel = np.array([[[a, y, a], [b, y, a], [b, y, b]], [[a, y, a], [b, y, b], [a, y, b]]], np.float32)
     scB = dict(scA, tri=np.concatenate([scA["tri"], panel]).astype(np.float32),
                albedo=np.concatenate([scA["albedo"], np.full((2, 3), 0.5)]).astype(np.float32),
                flags=np.concatenate([scA["flags"], np.zeros(2, np.uint8)]).astype(np.uint8))
     sidB = vplg.scene_upload(ctx, scB["tri"], scB["albedo"], scB["flags"], scB["light"])
     vp = vplg.vpls_download(ctx, vid)
-    assert (np.abs(vp["pos"][:vp["n"], 1]) < 1e-6).sum() > 10, "the plain box's set should hold floor VPLs"
+    assert (np.abs(vp["pos"][:vp["n"], 1]) < 1e-5).sum() > 10, "the plain room's set should hold floor VPLs"
     gb = vplg.GBuffer(W, Hh)
     vplg.gbuffer_render(ctx, sidB, scB["camera"], gb)
     L_gpu = _gather_gpu(vplg, ctx, sidB, vid, gb, prm)
     nd, n = OC.check_gather(vplg, ctx, orc.Scene.from_dict(scB), sidB, vid, gb, L_gpu, np.arange(W * Hh), prm,
-                            "plain-box VPLs in the panelled box", min_lit=0.1)
-    print(f"plain-box VPLs in the panelled box: {nd} grazing disagreements of {n} cast pairs")
+                            "plain-room VPLs in the panelled room", min_lit=0.05)
+    print(f"plain-room VPLs in the panelled room: {nd} grazing disagreements of {n} cast pairs")
     vplg.vplset_release(ctx, vid)
     vplg.scene_release(ctx, sidA)
     vplg.scene_release(ctx, sidB)
