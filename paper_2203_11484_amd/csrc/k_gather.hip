@@ -45,10 +45,12 @@ constexpr float kInvPi = 0.318309886183790671538f;
 // coordinate magnitude (plus 2^-12 of itself) against its FP32 rounding.
 constexpr float kFreeCoplanar = 4e-8f;
 constexpr float kFreeMargin = 2e-6f;
-// The radius is sought no farther than kFreeCap x the scene diagonal (the
-// walk prunes every box beyond it): the clipping gains little more from
-// larger radii, and a short walk is cheap.
-constexpr float kFreeCap = 0.05f;
+// The radius is sought no farther than a cap x the scene diagonal (the walk
+// prunes every box beyond it): a receiver's walk, once per tile inside the
+// gather, stops at kFreeCapTile (the clipping gains little more from larger
+// radii there), a VPL's, one wave per VPL before the gather, at kFreeCapVpl.
+constexpr float kFreeCapTile = 0.05f;
+constexpr float kFreeCapVpl = 0.2f;
 
 // Work memory of the allocation-free gather: the tile counter in the first
 // 256 bytes, then the round-group sums of at most kScratchSplitTiles split
@@ -510,12 +512,12 @@ __device__ __forceinline__ bool box_in_plane(float px, float py, float pz, float
 
 // Coplanarity tolerance, safety margin and squared cap of the free radius in
 // a scene.
-__device__ __forceinline__ void free_bounds(const DevScene& sc, float* tol, float* margin, float* cap2)
+__device__ __forceinline__ void free_bounds(const DevScene& sc, float cap, float* tol, float* margin, float* cap2)
 {
     const float dx = sc.hi[0] - sc.lo[0], dy = sc.hi[1] - sc.lo[1], dz = sc.hi[2] - sc.lo[2];
     const float diag = sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
     *tol = kFreeCoplanar * diag;
-    *cap2 = (kFreeCap * diag) * (kFreeCap * diag);
+    *cap2 = (cap * diag) * (cap * diag);
     const float big = fmaxf(fmaxf(fmaxf(fabsf(sc.lo[0]), fabsf(sc.hi[0])), fmaxf(fabsf(sc.lo[1]), fabsf(sc.hi[1]))),
                             fmaxf(fabsf(sc.lo[2]), fabsf(sc.hi[2])));
     *margin = kFreeMargin * big;
@@ -546,11 +548,11 @@ __device__ __forceinline__ float free_safe(float best2, float margin)
 // the dump, which walks the same tiles).  The search stops at the cap (a lane
 // with no triangle to consider within it gets the cap, shortened like any
 // radius); inactive lanes get 0.
-__device__ float free_radius(const DevScene& sc, float px, float py, float pz, float nx, float ny, float nz, int ex,
+__device__ float free_radius(const DevScene& sc, float cap, float px, float py, float pz, float nx, float ny, float nz, int ex,
                              bool act, int lane)
 {
     float tol, margin, cap2;
-    free_bounds(sc, &tol, &margin, &cap2);
+    free_bounds(sc, cap, &tol, &margin, &cap2);
     const float4* __restrict__ nodes = sc.nodes;
     const float4* __restrict__ tris = sc.tris;  // identity plane: vertices in (x, y, z) order
     // boxes are padded outward, so a box's distance is below that of any
@@ -722,7 +724,7 @@ __device__ __forceinline__ float3 gather_tile(const GatherArgs& a, int tile, int
     const bool active = valid && tp >= 0;
     // free radii of the tile's receivers: wave 0 of the group walks for them, the group reads them from
     // LDS (the slot is free until the group's first round-group sums)
-    if (wave == 0) red[0][0][lane] = a.free_ends & 1 ? free_radius(a.scene, x, y, z, nx, ny, nz, tp, active, lane) : 0.f;
+    if (wave == 0) red[0][0][lane] = a.free_ends & 1 ? free_radius(a.scene, kFreeCapTile, x, y, z, nx, ny, nz, tp, active, lane) : 0.f;
     sync();
     const float rx = red[0][0][lane];
     sync();
@@ -1049,7 +1051,7 @@ __global__ __launch_bounds__(BLOCK) void k_vis_dump(VisDumpArgs a)
             qpx = a.gb.pos[0][q]; qpy = a.gb.pos[1][q]; qpz = a.gb.pos[2][q];
             qnx = a.gb.nrm[0][q]; qny = a.gb.nrm[1][q]; qnz = a.gb.nrm[2][q];
         }
-        const float r = free_radius(a.scene, qpx, qpy, qpz, qnx, qny, qnz, qt, qv && qt >= 0, lane);
+        const float r = free_radius(a.scene, kFreeCapTile, qpx, qpy, qpz, qnx, qny, qnz, qt, qv && qt >= 0, lane);
         const float mine = __shfl(r, my_pos, 64);
         const bool here = ok && my_tile == T;
         if (here) rx = mine;
@@ -1238,7 +1240,7 @@ __global__ __launch_bounds__(64) void k_pack_vpls(DevScene sc, DevVpls v, int wi
     const float px = v.px[i], py = v.py[i], pz = v.pz[i];
     const float nx = v.nx[i], ny = v.ny[i], nz = v.nz[i];
     const int tri = v.tri[i];
-    const float r = with_radius ? free_radius(sc, px, py, pz, nx, ny, nz, tri, lane == 0, lane) : 0.f;
+    const float r = with_radius ? free_radius(sc, kFreeCapVpl, px, py, pz, nx, ny, nz, tri, lane == 0, lane) : 0.f;
     if (lane == 0) {
         v.pack[3 * i] = make_float4(px, py, pz, __int_as_float(tri));
         v.pack[3 * i + 1] = make_float4(nx, ny, nz, r);
