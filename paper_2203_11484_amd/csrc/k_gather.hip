@@ -97,9 +97,9 @@ __device__ __forceinline__ Rec load_rec(const float4* __restrict__ base, int idx
 
 __device__ __forceinline__ float safe_inv(float d)
 {
-    // A zero direction component would turn the slab test into 0 * inf; a
-    // tiny signed value keeps the slab unbounded on that axis instead.
-    return rcpf(fabsf(d) > 1e-30f ? d : copysignf(1e-30f, d));
+    // A zero direction component would turn the slab test into 0 * inf; the
+    // reciprocal clamped to +-1e30 keeps the slab unbounded on that axis.
+    return __builtin_amdgcn_fmed3f(rcpf(d), -1e30f, 1e30f);
 }
 
 // Counters of the instrumented gather.  Per lane: shadow rays cast, BVH node
@@ -624,7 +624,7 @@ __device__ __forceinline__ bool packet_visible(const DevScene& sc, float ox, flo
                                bool act, float tlo, float thi, int ex0, int ex1, float rx, float ry, int lane,
                                Counters& cnt)
 {
-    const float il = __builtin_amdgcn_rsqf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    const float il = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);  // the gather's r2, computed alike
     tlo = fmaxf(tlo, rx * il);
     thi = fminf(thi, fmaf(-ry, il, 1.0f));
     const bool open = act && !(tlo < thi);  // the whole range lies within the free radii
