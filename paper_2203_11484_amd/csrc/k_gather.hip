@@ -553,6 +553,8 @@ __device__ float free_radius(const DevScene& sc, float cap, float px, float py, 
 {
     float tol, margin, cap2;
     free_bounds(sc, cap, &tol, &margin, &cap2);
+    // without a unit normal there is no plane to leave: such a point gets 0
+    act = act && fmaf(nz, nz, fmaf(ny, ny, nx * nx)) > 0.5f;
     const float4* __restrict__ nodes = sc.nodes;
     const float4* __restrict__ tris = sc.tris;  // identity plane: vertices in (x, y, z) order
     // boxes are padded outward, so a box's distance is below that of any
