@@ -6,9 +6,11 @@ G-buffer render and VPL generation, a served request's lone twin).  Then:
 
 * visibility: the GPU's bits (the gather's own shadow-ray code, through the visibility dump) against the
   oracle's plain definition, pair by pair; every disagreement must be grazing (moving an endpoint by BAND =
-  1e-7 of the scene diagonal along a coordinate axis flips the oracle's answer: 1.4e-6 in the rooms, about
-  one and a half FP32 ulps of their coordinates) and, over the pairs whose shadow ray the gather casts, at
-  most 1e-4 of them;
+  1e-6 of the scene diagonal along a coordinate axis flips the oracle's answer: 1.5e-5 in the rooms, about
+  fifteen FP32 ulps of their coordinates; a segment between two points of one flat face lies in the face's
+  plane, where the face's own triangles, rounded to FP32, sit a few 1e-7 off it and cross it: the GPU's
+  parallel cut passes them, the oracle meets them, and only moves of about 1e-6 of the diagonal flip that)
+  and, over the pairs whose shadow ray the gather casts, at most 1e-4 of them;
 * radiance: per channel within 1e-4 relative (floor 1e-3 of the channel mean, exact zeros stay zero), with
   the oracle re-evaluated on the GPU's bit for the disagreeing pairs.
 """
@@ -17,7 +19,7 @@ import numpy as np
 from tests import helpers as H
 
 # grazing band of the visibility protocol, relative to the scene's bounding-box diagonal
-BAND = 1e-7
+BAND = 1e-6
 
 
 def dump_visibility(vplg, ctx, sid, vid, gb, pixels, M, prm):

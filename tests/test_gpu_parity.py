@@ -3,7 +3,7 @@
 Gather: the oracle's G-buffer and VPL set (rounded to float32) feed both
 sides, or (the device path) the G-buffer and VPL set the GPU made are
 downloaded and fed to the oracle.  Every visibility disagreement must be
-grazing (moving an endpoint by 1e-7 of the scene diagonal flips the oracle's
+grazing (moving an endpoint by 1e-6 of the scene diagonal flips the oracle's
 answer) and at most 1e-4 of the pairs; radiance must then match per channel
 within 1e-4 relative, with the oracle re-evaluated on the GPU's bit for the
 disagreeing pairs (tests/oracle_check.py).
@@ -93,22 +93,22 @@ def test_gather_every_tile_shape(vplg, ctx, tile_vpl):
 
 
 def test_gather_room20k_sampled(vplg, ctx):
-    """20k-triangle room at its full 512^2 size and 4096 VPLs; 384 sampled pixels checked pair by pair."""
+    """20k-triangle room at its full 512^2 size and 4096 VPLs; 1,536 sampled pixels checked pair by pair."""
     sc = scenes.make_scene("room20k")
     S, gbo, vp, _ = _oracle_inputs(sc)
     rng = np.random.default_rng(7)
-    pixels = np.sort(rng.choice(512 * 512, 384, replace=False))
+    pixels = np.sort(rng.choice(512 * 512, 1536, replace=False))
     nd, n = _check_gather(vplg, ctx, sc, S, gbo, vp, pixels, sc["params"], "room20k")
     print(f"room20k: {nd} grazing disagreements of {n} pairs")
 
 
 def test_gather_room200k_sampled(vplg, ctx):
     """202k-triangle room at its full 1920x1080 size and 16,384 VPLs, in the bench's launch configuration;
-    96 sampled pixels checked pair by pair (1.6M pairs)."""
+    480 sampled pixels checked pair by pair (7.9M pairs)."""
     sc = scenes.make_scene("room200k")
     S, gbo, vp, _ = _oracle_inputs(sc)
     rng = np.random.default_rng(9)
-    pixels = np.sort(rng.choice(1920 * 1080, 96, replace=False))
+    pixels = np.sort(rng.choice(1920 * 1080, 480, replace=False))
     nd, n = _check_gather(vplg, ctx, sc, S, gbo, vp, pixels, sc["params"], "room200k")
     print(f"room200k: {nd} grazing disagreements of {n} cast pairs")
 
@@ -183,7 +183,7 @@ def test_gbuffer_parity(vplg, ctx, name, size):
     vplg.scene_release(ctx, sid)
 
 
-DEVICE_CASES = [("cornell", None, 0, 0), ("room20k", 384, 11, 32), ("room200k", 96, 13, 32)]
+DEVICE_CASES = [("cornell", None, 0, 0), ("room20k", 1536, 11, 32), ("room200k", 480, 13, 32)]
 
 
 def _tail_pixels(W, H, n_tail, seed):

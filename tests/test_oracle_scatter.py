@@ -185,9 +185,9 @@ def _square_occluder(s=1.0, z=0.5, x0=0.0):
     return np.array([[A, B, C], [A, C, D]], np.float32)
 
 
-@pytest.mark.parametrize("delta_rel", [1e-5, 1e-7])
+@pytest.mark.parametrize("delta_rel", [1e-5, 1e-6, 1e-7])
 def test_grazing_flags_only_pairs_within_the_band(delta_rel):
-    """At the GPU parity protocol's band (1e-7 of the diagonal) and a wider one.  The square spans x in
+    """At the GPU parity protocol's band (1e-6 of the diagonal), a wider and a narrower one.  The square spans x in
     [-2, 0], so the points near its edge x = 0 are exact in float32 even 0.2 band widths from it."""
     tri = _square_occluder(x0=-1.0)
     S = orc.Scene(tri, np.full((2, 3), 0.5, np.float32), np.zeros(2, np.uint8), use_bvh=False)
@@ -217,7 +217,7 @@ def test_grazing_flags_only_pairs_within_the_band(delta_rel):
     assert graz.tolist() == [g for _, _, _, g in xs]
 
 
-@pytest.mark.parametrize("delta_rel", [1e-5, 1e-7])
+@pytest.mark.parametrize("delta_rel", [1e-5, 1e-6, 1e-7])
 def test_grazing_flags_crossings_at_the_segment_ends(delta_rel):
     """A crossing just inside the shadow segment's end range s > t_eps flips under the perturbation; one
     in the middle does not."""
